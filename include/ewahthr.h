@@ -1,0 +1,191 @@
+/*
+ * ewahthr.h -- C ABI of the MI355X (gfx950) T-of-N threshold library.
+ *
+ * Operation (Section 2, Formulation, of Kaser & Lemire, "Compressed bitmap
+ * indexes: beyond unions and intersections"): given N bitmaps over the same r
+ * rows and a threshold T, the result has row i set iff at least T of the N
+ * inputs have row i set.  T = 1 is the union, T = N the intersection.  The
+ * library extends the paper's range 1 <= T <= N to all T: T = 0 gives all ones
+ * over the r rows, T > N gives all zeros, N = 0 gives all ones for T = 0 and
+ * all zeros otherwise; an input listed twice counts twice.
+ *
+ * Bitmap format: EWAH with 64-bit words (Section 3.1, Compressed Bitmaps).  Row
+ * i is bit (i mod 64) of uncompressed word floor(i / 64), least-significant
+ * bit first (Section 3.1, Uncompressed Bitmaps).  A stream is a sequence of
+ * marker words, each followed by K dirty ("literal") words; a marker holds the
+ * fill bit in bit 0, the number L of fill words in bits 1..32 and K in bits
+ * 33..63 (the paper defers the exact layout to the EWAH format paper and notes
+ * 32-bit run counters; this is the reading adopted).  Inputs may be any
+ * well-formed stream (split runs, empty markers, fill-valued literal words);
+ * they must cover exactly U = ceil(r / 64) words and must not end inside a
+ * literal run.  Padding bits past row r - 1 are ignored.  Outputs are always
+ * canonical: every word equal to 0 or ~0 is a fill; a marker starts at word 0
+ * and at every fill word that follows a literal or a fill of the other value;
+ * literals attach to the preceding marker; trailing zero fills are explicit.
+ *
+ * All entry points return an ewah_status; on failure ewah_last_error() gives
+ * a message (thread-local).  No exception crosses the ABI.  Memory ownership
+ * is stated per call.  The library keeps one device (ewah_init) and is not
+ * thread-safe: calls must come from one host thread at a time.
+ */
+#ifndef EWAHTHR_H
+#define EWAHTHR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EWAH_OK = 0,
+    EWAH_EINVAL = -1,   /* bad argument: null pointer, mismatched n_bits, size limits */
+    EWAH_EFORMAT = -2,  /* malformed EWAH stream */
+    EWAH_ENOMEM = -3,   /* host or device allocation failed */
+    EWAH_ENOSPC = -4,   /* output capacity below ewah_output_bound() */
+    EWAH_EDEVICE = -5   /* HIP runtime error, wrong device, or a device-side error flag */
+} ewah_status;
+
+/* A borrowed EWAH stream: n_words 64-bit words describing n_bits rows. */
+typedef struct {
+    const uint64_t* words;
+    uint64_t n_words;
+    uint64_t n_bits;
+} ewah_view;
+
+/* Library-owned registered bitmap (device-resident words plus indexes). */
+typedef struct ewah_bitmap ewah_bitmap;
+
+/* Per-bitmap catalog, computed at registration. */
+typedef struct {
+    uint64_t n_bits;
+    uint64_t n_words;          /* compressed words (EWAHSize / 8) */
+    uint64_t n_markers;
+    uint64_t n_literals;       /* dirty words */
+    uint64_t one_fill_words;   /* uncompressed words covered by fills of ones */
+    uint64_t popcount;         /* number of rows set (|B_i|) */
+    uint64_t run_count;        /* RunCount: runs of 0s and 1s over the r rows (Section 3.1) */
+    uint64_t index_bytes;      /* device bytes of the locator and skip index */
+} ewah_stats;
+
+/* Selects the HIP device (must be gfx950) and allocates library state.  Idempotent. */
+ewah_status ewah_init(int device);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* ewah_last_error(void);
+
+/*
+ * Registration (data loading, not part of a query; the paper likewise assumes
+ * the bitmaps are in memory before a query, Section 2).  Validates the stream,
+ * copies it to device memory and builds the per-tile locator (for every 1024
+ * uncompressed words, the marker whose run covers that word) and the skip
+ * index (for every 64 compressed words, the position of the first word and the
+ * offset of the first marker).  v->words is a host pointer if on_device == 0,
+ * else a device pointer; it is only read during the call.  The call is
+ * synchronous.  Limits: n_bits < 2^37 (U < 2^31 words).  EFORMAT if the stream
+ * is malformed.  *out is owned by the caller until ewah_release().
+ */
+ewah_status ewah_register(const ewah_view* v, int on_device, ewah_bitmap** out);
+
+/* Same for count bitmaps at once (one device allocation); out[i] for v[i]. */
+ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device, ewah_bitmap** out);
+
+/* Frees a registered bitmap.  No query using it may still be in flight. */
+void ewah_release(ewah_bitmap* b);
+
+ewah_status ewah_get_stats(const ewah_bitmap* b, ewah_stats* out);
+
+/* Device address of the registered stream (for tests and tools; read-only). */
+const uint64_t* ewah_device_words(const ewah_bitmap* b);
+
+/*
+ * Upper bound on the canonical output length in words for inputs of
+ * sum_input_words words in total over n_bits rows: 0 if n_bits = 0, else
+ * min(U + 1, sum_input_words + 2).  Every output word is charged to a distinct
+ * input word at the same position (an output dirty word needs an input dirty
+ * word there; an output marker needs an input dirty word or an input run
+ * starting there), plus the head marker and one dirty word for N = 0.
+ */
+uint64_t ewah_output_bound(uint64_t n_bits, uint64_t sum_input_words);
+
+/*
+ * T-of-N threshold of in[0..n-1] (registered, equal n_bits, 1 <= n <= 4095;
+ * n = 0 is EINVAL since the row count would be undefined).
+ * Writes the canonical EWAH result to out_words_dev (device memory, caller
+ * owned, out_cap words) and its length to *out_n_words_dev (device memory).
+ * out_cap must be >= ewah_output_bound(n_bits, sum of input n_words), else
+ * ENOSPC without any device work.  The work is enqueued on hip_stream (a
+ * hipStream_t, NULL = default stream) and the call returns without waiting;
+ * inputs must stay registered until it completes.  Concurrent calls on
+ * different streams are allowed.
+ */
+ewah_status ewah_threshold(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
+                           uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream);
+
+/* As ewah_threshold with an explicit kernel variant (ewah_variant_code); the result is identical. */
+ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
+                             uint64_t out_cap, uint64_t* out_n_words_dev, uint32_t variant, void* hip_stream);
+
+/*
+ * Kernel variant code: dense = 1 sends inputs whose dirty run covers a whole
+ * tile through the register carry-save-adder tree; walk / litwalk (0..255)
+ * are the longest compressed segment / dirty block handled by a single lane
+ * before it is split across a wavefront.
+ */
+uint32_t ewah_variant_code(int dense, uint32_t walk, uint32_t litwalk);
+uint32_t ewah_default_variant(void);
+
+/* ------------------------------------------------------------ batched path */
+
+/* One query of a batch: indices into the batch's pool. idx is host memory, read during planning. */
+typedef struct {
+    const uint32_t* idx;
+    uint32_t n;
+    uint32_t T;
+    uint64_t* out_words_dev;     /* device, caller owned, >= ewah_output_bound() words */
+    uint64_t out_cap;
+    uint64_t* out_n_words_dev;   /* device, caller owned */
+    uint32_t variant;            /* 0 = library default */
+} ewah_query;
+
+typedef struct {
+    uint32_t grid;          /* persistent workgroups, 0 = one per compute unit */
+    int use_graph;          /* 1 = capture bump + persistent kernel into a hipGraph */
+} ewah_batch_config;
+
+typedef struct ewah_batch ewah_batch;
+
+/*
+ * Plans a batch: uploads the query table (inputs as pool indices, thresholds,
+ * output pointers, variants) and, with use_graph, captures the launch into a
+ * HIP graph.  pool[] must stay registered while the batch exists.  All pool
+ * bitmaps must have the same n_bits > 0.  Synchronous.
+ */
+ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, const ewah_query* q, uint32_t nq,
+                            const ewah_batch_config* cfg, ewah_batch** out);
+
+/* Runs every query of the batch in one persistent launch on hip_stream (asynchronous). */
+ewah_status ewah_batch_run(ewah_batch* b, void* hip_stream);
+
+/* Replaces the per-query variants (nq entries, 0 = default).  Synchronous. */
+ewah_status ewah_batch_set_variants(ewah_batch* b, const uint32_t* variants);
+
+/* Sets the persistent grid size (workgroups); rebuilds the graph.  Synchronous. */
+ewah_status ewah_batch_set_grid(ewah_batch* b, uint32_t grid);
+
+void ewah_batch_free(ewah_batch* b);
+
+/*
+ * Reads and clears the device-side error flags (synchronises the device):
+ * bit 0 = a tile's look-back wait gave up, bit 1 = a look-back ran past tile 0.
+ * Either means the outputs of that launch are invalid.
+ */
+ewah_status ewah_device_errors(uint32_t* flags);
+
+/* Number of compute units of the device (0 before ewah_init). */
+uint32_t ewah_num_cus(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EWAHTHR_H */

@@ -1,0 +1,582 @@
+// Host runtime of the threshold library: registration (validation, locator and
+// skip-index construction), device bitmap table, per-stream query contexts,
+// batched plans with HIP graph capture, and the C ABI of include/ewahthr.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/ewahthr.h"
+#include "thr_device.h"
+
+using namespace ewt;
+
+namespace {
+
+thread_local std::string g_err;
+
+ewah_status fail(ewah_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(EWAH_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+struct Arena {
+    void* d = nullptr;
+    int refs = 0;
+};
+
+}  // namespace
+
+struct ewah_bitmap {
+    BitmapDev dev;        // device pointers into the arena
+    uint32_t slot = 0;    // index in the device table
+    ewah_stats stats{};
+    Arena* arena = nullptr;
+};
+
+namespace {
+
+struct Ctx {                       // per-stream query state
+    uint32_t* d_ids = nullptr;
+    size_t ids_cap = 0;
+    uint32_t* h_ids = nullptr;     // pinned staging
+    TileState* d_state = nullptr;
+    size_t state_cap = 0;
+    uint32_t* d_ticket = nullptr;
+    uint32_t epoch = 0;
+    hipEvent_t ev = nullptr;       // staging buffer free once this completes
+};
+
+struct Lib {
+    bool ready = false;
+    int device = -1;
+    uint32_t n_cu = 0;
+    size_t max_smem = 0;
+    std::vector<BitmapDev> table;  // host mirror
+    std::vector<uint32_t> free_slots;
+    BitmapDev* d_table = nullptr;
+    size_t d_table_cap = 0;
+    uint32_t* d_err = nullptr;
+    std::map<hipStream_t, Ctx> ctx;
+};
+
+Lib g;
+
+ewah_status ensure_ready() {
+    if (!g.ready) return fail(EWAH_EINVAL, "ewah_init() has not been called");
+    return EWAH_OK;
+}
+
+// ----------------------------------------------------------- index builder
+
+struct Built {
+    std::vector<uint2> loc, skip;
+    ewah_stats st{};
+};
+
+inline uint64_t popc64(uint64_t x) { return (uint64_t)__builtin_popcountll(x); }
+
+// Validates one stream and builds its locator and skip index (one pass).
+ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& b) {
+    const uint64_t U = (n_bits + 63) / 64;
+    if (U >= (1ull << 31)) return fail(EWAH_EINVAL, "n_bits too large (U must be < 2^31 words)");
+    if (nw >= (1ull << 32) - CHUNK) return fail(EWAH_EINVAL, "stream too long (n_words must be < 2^32 - 64)");
+    const uint64_t tiles = (U + TW - 1) / TW;
+    const uint64_t nchunks = (nw + CHUNK - 1) / CHUNK;
+    b.loc.assign(tiles + 1, make_uint2(0, 0));
+    b.skip.assign(nchunks, make_uint2(0, 64));
+    const uint64_t tailmask = (n_bits % 64) ? ((1ull << (n_bits % 64)) - 1) : ~0ull;
+    ewah_stats& st = b.st;
+    st = ewah_stats{};
+    st.n_bits = n_bits;
+    st.n_words = nw;
+    uint64_t p = 0, u = 0;
+    int prev_bit = -1;   // last row bit, for RunCount
+    auto run_bits = [&](uint64_t v, uint64_t nbits) {  // count runs over the next nbits rows of v
+        if (nbits == 0) return;
+        uint64_t m = nbits == 64 ? ~0ull : ((1ull << nbits) - 1);
+        uint64_t x = v & m;
+        uint64_t shifted = (x << 1) | (uint64_t)(prev_bit < 0 ? (x & 1) : (uint64_t)prev_bit);
+        uint64_t changes = (x ^ shifted) & m;
+        st.run_count += popc64(changes) + (prev_bit < 0 ? 1 : 0);
+        prev_bit = (int)((x >> (nbits - 1)) & 1);
+    };
+    while (p < nw) {
+        const uint64_t m = w[p];
+        const uint64_t f = m & 1, L = (m >> 1) & 0xFFFFFFFFull, K = m >> 33;
+        if (L > U - u) return fail(EWAH_EFORMAT, "marker at word " + std::to_string(p) + ": fill run past the end");
+        if (K > nw - p - 1) return fail(EWAH_EFORMAT, "marker at word " + std::to_string(p) + ": stream ends inside its literal run");
+        if (K > U - u - L) return fail(EWAH_EFORMAT, "marker at word " + std::to_string(p) + ": literal run past the end");
+        st.n_markers++;
+        const uint64_t c = p / CHUNK;
+        if (b.skip[c].y == 64) b.skip[c].y = (uint32_t)(p - c * CHUNK);
+        if (p % CHUNK == 0) b.skip[c].x = (uint32_t)u;
+        if (L + K > 0) {
+            for (uint64_t t = (u + TW - 1) / TW; t * TW < u + L + K && t < tiles; ++t) b.loc[t] = make_uint2((uint32_t)p, (uint32_t)u);
+        }
+        // statistics over the fill run
+        if (L) {
+            uint64_t last_in_run = (u + L == U) ? 1 : 0;
+            if (f) {
+                st.one_fill_words += L;
+                st.popcount += (L - last_in_run) * 64 + (last_in_run ? popc64(tailmask) : 0);
+            }
+            // a fill run contributes one run boundary at most
+            uint64_t rows = (L - last_in_run) * 64 + (last_in_run ? (n_bits - (U - 1) * 64) : 0);
+            if (rows) {
+                if (prev_bit != (int)f) st.run_count++;
+                prev_bit = (int)f;
+            }
+        }
+        for (uint64_t i = 0; i < K; ++i) {
+            const uint64_t q = p + 1 + i, pos = u + L + i;
+            if (q % CHUNK == 0) b.skip[q / CHUNK].x = (uint32_t)pos;
+            uint64_t v = w[q];
+            const uint64_t nbits = (pos == U - 1) ? (n_bits - (U - 1) * 64) : 64;
+            if (pos == U - 1) v &= tailmask;
+            st.popcount += popc64(v);
+            run_bits(v, nbits);
+        }
+        st.n_literals += K;
+        p += 1 + K;
+        u += L + K;
+    }
+    if (u != U) return fail(EWAH_EFORMAT, "stream covers " + std::to_string(u) + " words, expected " + std::to_string(U));
+    if (tiles) b.loc[tiles] = make_uint2((uint32_t)nw, (uint32_t)U);
+    st.index_bytes = (b.loc.size() + b.skip.size()) * sizeof(uint2);
+    return EWAH_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+ewah_status table_sync() {
+    // grow the device table if needed and upload the host mirror
+    if (g.table.size() > g.d_table_cap) {
+        size_t cap = std::max<size_t>(1024, g.d_table_cap * 2);
+        while (cap < g.table.size()) cap *= 2;
+        HIPCHK(hipDeviceSynchronize());
+        BitmapDev* nd = nullptr;
+        HIPCHK(hipMalloc(&nd, cap * sizeof(BitmapDev)));
+        if (g.d_table) HIPCHK(hipFree(g.d_table));
+        g.d_table = nd;
+        g.d_table_cap = cap;
+    }
+    if (!g.table.empty())
+        HIPCHK(hipMemcpy(g.d_table, g.table.data(), g.table.size() * sizeof(BitmapDev), hipMemcpyHostToDevice));
+    return EWAH_OK;
+}
+
+uint32_t alloc_slot() {
+    if (!g.free_slots.empty()) {
+        uint32_t s = g.free_slots.back();
+        g.free_slots.pop_back();
+        return s;
+    }
+    g.table.push_back(BitmapDev{});
+    return (uint32_t)(g.table.size() - 1);
+}
+
+ewah_status get_ctx(hipStream_t s, Ctx** out) {
+    auto it = g.ctx.find(s);
+    if (it == g.ctx.end()) {
+        Ctx c;
+        HIPCHK(hipMalloc(&c.d_ticket, 256));
+        HIPCHK(hipMemset(c.d_ticket, 0, 256));
+        HIPCHK(hipEventCreateWithFlags(&c.ev, hipEventDisableTiming));
+        it = g.ctx.emplace(s, c).first;
+    }
+    *out = &it->second;
+    return EWAH_OK;
+}
+
+ewah_status ctx_reserve(Ctx& c, hipStream_t s, size_t n_ids, size_t tiles) {
+    if (n_ids > c.ids_cap || tiles > c.state_cap) {
+        HIPCHK(hipStreamSynchronize(s));
+        if (n_ids > c.ids_cap) {
+            size_t cap = std::max<size_t>(n_ids, 1024);
+            if (c.d_ids) HIPCHK(hipFree(c.d_ids));
+            if (c.h_ids) HIPCHK(hipHostFree(c.h_ids));
+            HIPCHK(hipMalloc(&c.d_ids, cap * 4));
+            HIPCHK(hipHostMalloc(&c.h_ids, cap * 4, hipHostMallocDefault));
+            c.ids_cap = cap;
+        }
+        if (tiles > c.state_cap) {
+            size_t cap = std::max<size_t>(tiles, 1024);
+            if (c.d_state) HIPCHK(hipFree(c.d_state));
+            HIPCHK(hipMalloc(&c.d_state, cap * sizeof(TileState)));
+            HIPCHK(hipMemset(c.d_state, 0, cap * sizeof(TileState)));
+            c.state_cap = cap;
+            c.epoch = 0;
+        }
+    }
+    return EWAH_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char* ewah_last_error(void) { return g_err.c_str(); }
+
+ewah_status ewah_init(int device) {
+    if (g.ready) {
+        if (device != g.device) return fail(EWAH_EINVAL, "library already initialised on another device");
+        return EWAH_OK;
+    }
+    int n = 0;
+    HIPCHK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(EWAH_EINVAL, "no such device");
+    HIPCHK(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(EWAH_EDEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    g.device = device;
+    g.n_cu = (uint32_t)prop.multiProcessorCount;
+    g.max_smem = prop.sharedMemPerBlock;
+    size_t need = tile_smem_bytes(MAXN);
+    if (g.max_smem < need)
+        return fail(EWAH_EDEVICE, "device offers " + std::to_string(g.max_smem) + " B of LDS per workgroup, need " +
+                                      std::to_string(need));
+    HIPCHK(set_smem_limits(need));
+    HIPCHK(hipMalloc(&g.d_err, 256));
+    HIPCHK(hipMemset(g.d_err, 0, 256));
+    g.ready = true;
+    return EWAH_OK;
+}
+
+uint32_t ewah_num_cus(void) { return g.n_cu; }
+
+uint64_t ewah_output_bound(uint64_t n_bits, uint64_t sum_input_words) {
+    uint64_t U = (n_bits + 63) / 64;
+    if (U == 0) return 0;
+    return std::min<uint64_t>(U + 1, sum_input_words + 2);
+}
+
+uint32_t ewah_variant_code(int dense, uint32_t walk, uint32_t litwalk) { return var_make(dense != 0, walk, litwalk); }
+uint32_t ewah_default_variant(void) { return var_make(true, 8, 8); }
+
+ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device, ewah_bitmap** out) {
+    ewah_status st = ensure_ready();
+    if (st) return st;
+    if (count == 0) return EWAH_OK;
+    if (!v || !out) return fail(EWAH_EINVAL, "null argument");
+    std::vector<Built> built(count);
+    std::vector<std::vector<uint64_t>> host(count);
+    for (uint32_t i = 0; i < count; ++i) {
+        if (v[i].n_words && !v[i].words) return fail(EWAH_EINVAL, "null words pointer");
+        const uint64_t* w = v[i].words;
+        if (on_device && v[i].n_words) {
+            host[i].resize(v[i].n_words);
+            HIPCHK(hipMemcpy(host[i].data(), v[i].words, v[i].n_words * 8, hipMemcpyDeviceToHost));
+            w = host[i].data();
+        }
+        st = build_index(w, v[i].n_words, v[i].n_bits, built[i]);
+        if (st) return fail(st, "bitmap " + std::to_string(i) + ": " + g_err);
+    }
+    // one device arena: [words padded to CHUNK | skip | loc] per bitmap
+    std::vector<size_t> off(count + 1, 0);
+    for (uint32_t i = 0; i < count; ++i) {
+        size_t nch = built[i].skip.size();
+        size_t sz = align256(std::max<size_t>(nch, 1) * CHUNK * 8) + align256(std::max<size_t>(nch, 1) * 8) +
+                    align256(built[i].loc.size() * 8);
+        off[i + 1] = off[i] + sz;
+    }
+    Arena* arena = new Arena();
+    if (hipMalloc(&arena->d, off[count]) != hipSuccess) {
+        delete arena;
+        return fail(EWAH_ENOMEM, "device allocation of " + std::to_string(off[count]) + " bytes failed");
+    }
+    // zero the whole arena so chunk padding reads zeros
+    HIPCHK(hipMemset(arena->d, 0, off[count]));
+    for (uint32_t i = 0; i < count; ++i) {
+        char* base = (char*)arena->d + off[i];
+        size_t nch = std::max<size_t>(built[i].skip.size(), 1);
+        uint64_t* dw = (uint64_t*)base;
+        uint2* dskip = (uint2*)(base + align256(nch * CHUNK * 8));
+        uint2* dloc = (uint2*)(base + align256(nch * CHUNK * 8) + align256(nch * 8));
+        const uint64_t* src = on_device ? host[i].data() : v[i].words;
+        if (v[i].n_words) HIPCHK(hipMemcpy(dw, src, v[i].n_words * 8, hipMemcpyHostToDevice));
+        if (!built[i].skip.empty()) HIPCHK(hipMemcpy(dskip, built[i].skip.data(), built[i].skip.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dloc, built[i].loc.data(), built[i].loc.size() * 8, hipMemcpyHostToDevice));
+        ewah_bitmap* b = new ewah_bitmap();
+        b->dev.words = dw;
+        b->dev.loc = dloc;
+        b->dev.skip = dskip;
+        b->dev.n_words = (uint32_t)v[i].n_words;
+        b->dev.U = (uint32_t)((v[i].n_bits + 63) / 64);
+        b->stats = built[i].st;
+        b->arena = arena;
+        arena->refs++;
+        b->slot = alloc_slot();
+        g.table[b->slot] = b->dev;
+        out[i] = b;
+    }
+    return table_sync();
+}
+
+ewah_status ewah_register(const ewah_view* v, int on_device, ewah_bitmap** out) {
+    return ewah_register_many(v, 1, on_device, out);
+}
+
+void ewah_release(ewah_bitmap* b) {
+    if (!b) return;
+    g.table[b->slot] = BitmapDev{};
+    g.free_slots.push_back(b->slot);
+    if (--b->arena->refs == 0) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(b->arena->d);
+        delete b->arena;
+    }
+    delete b;
+}
+
+ewah_status ewah_get_stats(const ewah_bitmap* b, ewah_stats* out) {
+    if (!b || !out) return fail(EWAH_EINVAL, "null argument");
+    *out = b->stats;
+    return EWAH_OK;
+}
+
+const uint64_t* ewah_device_words(const ewah_bitmap* b) { return b ? b->dev.words : nullptr; }
+
+ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
+                             uint64_t out_cap, uint64_t* out_n_words_dev, uint32_t variant, void* hip_stream) {
+    ewah_status st = ensure_ready();
+    if (st) return st;
+    if ((n && !in) || !out_n_words_dev) return fail(EWAH_EINVAL, "null argument");
+    if (n > MAXN) return fail(EWAH_EINVAL, "at most " + std::to_string(MAXN) + " inputs per query");
+    if (n == 0) return fail(EWAH_EINVAL, "n = 0: the number of rows is undefined without an input");
+    uint64_t n_bits = 0, sum_words = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!in[i]) return fail(EWAH_EINVAL, "null bitmap at index " + std::to_string(i));
+        if (i == 0) n_bits = in[i]->stats.n_bits;
+        else if (in[i]->stats.n_bits != n_bits) return fail(EWAH_EINVAL, "inputs have different n_bits");
+        sum_words += in[i]->stats.n_words;
+    }
+    const uint64_t bound = ewah_output_bound(n_bits, sum_words);
+    if (out_cap < bound)
+        return fail(EWAH_ENOSPC, "out_cap " + std::to_string(out_cap) + " < bound " + std::to_string(bound));
+    if (bound && !out_words_dev) return fail(EWAH_EINVAL, "null output");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const uint32_t U = (uint32_t)((n_bits + 63) / 64);
+    if (U == 0) {
+        HIPCHK(launch_zero_len(out_n_words_dev, s));
+        return EWAH_OK;
+    }
+    const uint32_t tiles = (U + TW - 1) / TW;
+    Ctx* c = nullptr;
+    st = get_ctx(s, &c);
+    if (st) return st;
+    st = ctx_reserve(*c, s, n, tiles);
+    if (st) return st;
+    HIPCHK(hipEventSynchronize(c->ev));   // previous upload from the staging buffer is done
+    for (uint32_t i = 0; i < n; ++i) c->h_ids[i] = in[i]->slot;
+    HIPCHK(hipMemcpyAsync(c->d_ids, c->h_ids, (size_t)n * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(c->ev, s));
+    if (++c->epoch == 0) {   // wrapped: clear stale flags
+        HIPCHK(hipMemsetAsync(c->d_state, 0, c->state_cap * sizeof(TileState), s));
+        c->epoch = 1;
+    }
+    QueryDev q;
+    q.ids = c->d_ids;
+    q.out = out_words_dev;
+    q.out_n = out_n_words_dev;
+    q.state = c->d_state;
+    q.cap = out_cap;
+    q.N = n;
+    q.T = T;
+    q.U = U;
+    q.tiles = tiles;
+    q.tail_bits = (uint32_t)(n_bits % 64);
+    q.variant = variant ? variant : ewah_default_variant();
+    HIPCHK(launch_query(q, g.d_table, c->d_ticket, c->epoch, g.d_err, s));
+    return EWAH_OK;
+}
+
+ewah_status ewah_threshold(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
+                           uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream) {
+    return ewah_threshold_v(in, n, T, out_words_dev, out_cap, out_n_words_dev, 0, hip_stream);
+}
+
+ewah_status ewah_device_errors(uint32_t* flags) {
+    ewah_status st = ensure_ready();
+    if (st) return st;
+    HIPCHK(hipDeviceSynchronize());
+    uint32_t v = 0;
+    HIPCHK(hipMemcpy(&v, g.d_err, 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemset(g.d_err, 0, 4));
+    if (flags) *flags = v;
+    return EWAH_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------- batches
+
+struct ewah_batch {
+    std::vector<QueryDev> h_qs;
+    QueryDev* d_qs = nullptr;
+    uint32_t* d_qtile = nullptr;
+    uint32_t* d_ids = nullptr;
+    TileState* d_state = nullptr;
+    uint32_t* d_work = nullptr;    // work counter, epoch
+    uint32_t nq = 0;
+    uint32_t grid = 0;
+    size_t smem = 0;
+    int use_graph = 1;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+ewah_status batch_build_graph(ewah_batch* b) {
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    if (!b->use_graph) return EWAH_OK;
+    if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = launch_bump(b->d_work + 1, b->cap_stream);
+    hipError_t e2 = launch_batch(b->d_qs, b->d_qtile, b->nq, g.d_table, b->d_work, b->d_work + 1, g.d_err, b->grid,
+                                 b->smem, b->cap_stream);
+    hipError_t e3 = hipStreamEndCapture(b->cap_stream, &b->graph);
+    HIPCHK(e1);
+    HIPCHK(e2);
+    HIPCHK(e3);
+    HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return EWAH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, const ewah_query* q, uint32_t nq,
+                            const ewah_batch_config* cfg, ewah_batch** out) {
+    ewah_status st = ensure_ready();
+    if (st) return st;
+    if (!pool || !q || !out || nq == 0) return fail(EWAH_EINVAL, "null argument or empty batch");
+    uint64_t n_bits = 0;
+    for (uint32_t i = 0; i < pool_n; ++i) {
+        if (!pool[i]) return fail(EWAH_EINVAL, "null pool bitmap");
+        if (i == 0) n_bits = pool[i]->stats.n_bits;
+        else if (pool[i]->stats.n_bits != n_bits) return fail(EWAH_EINVAL, "pool bitmaps have different n_bits");
+    }
+    const uint32_t U = (uint32_t)((n_bits + 63) / 64);
+    if (U == 0) return fail(EWAH_EINVAL, "batched queries need n_bits > 0");
+    const uint32_t tiles = (U + TW - 1) / TW;
+    std::unique_ptr<ewah_batch> b(new ewah_batch());
+    b->nq = nq;
+    std::vector<uint32_t> ids;
+    std::vector<uint32_t> qtile(nq + 1, 0);
+    std::vector<size_t> id_off(nq);
+    uint32_t maxN = 1;
+    for (uint32_t i = 0; i < nq; ++i) {
+        if (q[i].n == 0 || q[i].n > MAXN || !q[i].idx || !q[i].out_n_words_dev || !q[i].out_words_dev)
+            return fail(EWAH_EINVAL, "query " + std::to_string(i) + ": bad arguments");
+        uint64_t sum = 0;
+        id_off[i] = ids.size();
+        for (uint32_t k = 0; k < q[i].n; ++k) {
+            uint32_t j = q[i].idx[k];
+            if (j >= pool_n) return fail(EWAH_EINVAL, "query " + std::to_string(i) + ": pool index out of range");
+            ids.push_back(pool[j]->slot);
+            sum += pool[j]->stats.n_words;
+        }
+        uint64_t bound = ewah_output_bound(n_bits, sum);
+        if (q[i].out_cap < bound)
+            return fail(EWAH_ENOSPC, "query " + std::to_string(i) + ": out_cap below bound " + std::to_string(bound));
+        maxN = std::max(maxN, q[i].n);
+        qtile[i + 1] = qtile[i] + tiles;
+    }
+    if ((uint64_t)qtile[nq] * 1 >= (1ull << 31)) return fail(EWAH_EINVAL, "too many tiles in one batch");
+    HIPCHK(hipMalloc(&b->d_ids, ids.size() * 4));
+    HIPCHK(hipMemcpy(b->d_ids, ids.data(), ids.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMalloc(&b->d_state, (size_t)qtile[nq] * sizeof(TileState)));
+    HIPCHK(hipMemset(b->d_state, 0, (size_t)qtile[nq] * sizeof(TileState)));
+    HIPCHK(hipMalloc(&b->d_qtile, (nq + 1) * 4));
+    HIPCHK(hipMemcpy(b->d_qtile, qtile.data(), (nq + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMalloc(&b->d_work, 256));
+    HIPCHK(hipMemset(b->d_work, 0, 256));
+    b->h_qs.resize(nq);
+    for (uint32_t i = 0; i < nq; ++i) {
+        QueryDev& d = b->h_qs[i];
+        d.ids = b->d_ids + id_off[i];
+        d.out = q[i].out_words_dev;
+        d.out_n = q[i].out_n_words_dev;
+        d.state = b->d_state + qtile[i];
+        d.cap = q[i].out_cap;
+        d.N = q[i].n;
+        d.T = q[i].T;
+        d.U = U;
+        d.tiles = tiles;
+        d.tail_bits = (uint32_t)(n_bits % 64);
+        d.variant = q[i].variant ? q[i].variant : ewah_default_variant();
+    }
+    HIPCHK(hipMalloc(&b->d_qs, nq * sizeof(QueryDev)));
+    HIPCHK(hipMemcpy(b->d_qs, b->h_qs.data(), nq * sizeof(QueryDev), hipMemcpyHostToDevice));
+    b->smem = tile_smem_bytes(maxN);
+    b->grid = (cfg && cfg->grid) ? cfg->grid : g.n_cu;
+    b->use_graph = cfg ? cfg->use_graph : 1;
+    st = batch_build_graph(b.get());
+    if (st) return st;
+    *out = b.release();
+    return EWAH_OK;
+}
+
+ewah_status ewah_batch_run(ewah_batch* b, void* hip_stream) {
+    if (!b) return fail(EWAH_EINVAL, "null batch");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (b->exec) {
+        HIPCHK(hipGraphLaunch(b->exec, s));
+    } else {
+        HIPCHK(launch_bump(b->d_work + 1, s));
+        HIPCHK(launch_batch(b->d_qs, b->d_qtile, b->nq, g.d_table, b->d_work, b->d_work + 1, g.d_err, b->grid, b->smem, s));
+    }
+    return EWAH_OK;
+}
+
+ewah_status ewah_batch_set_variants(ewah_batch* b, const uint32_t* variants) {
+    if (!b || !variants) return fail(EWAH_EINVAL, "null argument");
+    for (uint32_t i = 0; i < b->nq; ++i) b->h_qs[i].variant = variants[i] ? variants[i] : ewah_default_variant();
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(b->d_qs, b->h_qs.data(), b->nq * sizeof(QueryDev), hipMemcpyHostToDevice));
+    return EWAH_OK;
+}
+
+ewah_status ewah_batch_set_grid(ewah_batch* b, uint32_t grid) {
+    if (!b || grid == 0) return fail(EWAH_EINVAL, "bad argument");
+    HIPCHK(hipDeviceSynchronize());
+    b->grid = grid;
+    return batch_build_graph(b);
+}
+
+void ewah_batch_free(ewah_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    (void)hipFree(b->d_qs);
+    (void)hipFree(b->d_qtile);
+    (void)hipFree(b->d_ids);
+    (void)hipFree(b->d_state);
+    (void)hipFree(b->d_work);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Device-side data structures and the per-tile routine of the T-of-N threshold
+// query over EWAH bitmaps (64-bit words), written for gfx950 (wave64, 160 KB LDS).
+//
+// One workgroup computes the output of one tile of TW consecutive uncompressed
+// word positions (TW * 64 rows) over all N inputs:
+//   1. segment location: per input, the per-tile locator built at registration
+//      gives the marker whose run covers the tile start; its header and the
+//      header of the marker covering the next tile start bound the input's
+//      compressed words that touch the tile (EWAH markers carry both the fill
+//      length and the dirty-word count, so dirty runs are skipped without
+//      reading them -- Section 3.1);
+//   2. classify / prune: inputs whose one-fill covers the whole tile and inputs
+//      that can hold a one in the tile are counted; the three cases of RBMrg on
+//      EWAH (Section 6.4) at tile granularity: >= T full one-fills -> all ones,
+//      fewer than T non-empty inputs -> all zeros, else count;
+//   3. decode: short segments are walked by one lane; long ones are split into
+//      64-word windows aligned to the compressed stream, each decoded by one
+//      wavefront: a skip-index entry gives the first marker of the window, the
+//      marker chain (next = p + 1 + K) is resolved by pointer doubling across the
+//      wavefront, and a wavefront prefix scan of (L + K) over the markers gives
+//      every word's uncompressed position;
+//   4. count: dirty words are added into a bit-sliced per-row counter in LDS
+//      (planes A_1..A_P, least significant first, as in the bit-sliced index of
+//      Section 5.3.1) with an atomic ripple-carry add (ScanCount with bit-sliced
+//      counters, Section 5.1); inputs whose dirty run covers the whole tile go
+//      through a dense carry-save-adder (Harley-Seal) tree in registers, one
+//      lane per word position; one-fills are counted per position through a
+//      difference array;
+//   5. compare: per word position, the bit-sliced count is compared with
+//      T' = T - (number of one-fills at that position) (greater-than-or-equal,
+//      cf. the comparison step of BSTM, Section 5.3.1);
+//   6. encode: canonical EWAH by scan-and-compact; the tile's run structure is
+//      summarised in an associative aggregate and the exclusive prefix over
+//      earlier tiles is obtained by decoupled look-back, so markers spanning
+//      tiles are closed by the tile that holds the next marker.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ewt {
+
+constexpr int TW = 1024;          // tile width in uncompressed 64-bit words (= locator granularity)
+constexpr int BLOCK = 1024;       // threads per workgroup (one per word position of a tile)
+constexpr int NWAVES = BLOCK / 64;
+constexpr int CHUNK = 64;         // compressed words per skip-index entry
+constexpr int MAXP = 12;          // bit planes: inputs per query < 2^12 (LDS budget)
+constexpr uint32_t MAXN = (1u << MAXP) - 1;
+
+// Registered bitmap as seen by the kernels (32 bytes).
+struct BitmapDev {
+    const uint64_t* words;   // EWAH stream, zero-padded to a multiple of CHUNK words
+    const uint2* loc;        // tiles + 1 entries: (marker index, its run start) covering tile start
+    const uint2* skip;       // one per CHUNK words: (position of the chunk's first word, first marker offset or 64)
+    uint32_t n_words;
+    uint32_t U;              // uncompressed words
+};
+
+// Associative run-structure aggregate of a range of output words (see encode step).
+struct Agg {
+    uint32_t n;        // emitted compressed words, first word counted as a head if it is a fill
+    uint32_t lh_pos;   // position of the last head (marker) in the range
+    uint32_t lh_out;   // its output index relative to the range's first output word
+    uint32_t bits;     // cf | cl << 2 | has_head << 4 | last head fill bit << 5
+};
+
+struct TileState {        // 48 bytes, one per (query, tile)
+    Agg local;
+    Agg incl;
+    uint32_t flag_local;
+    uint32_t flag_incl;
+    uint32_t pad[2];
+};
+
+struct QueryDev {         // 64 bytes
+    const uint32_t* ids;  // N bitmap slots
+    uint64_t* out;        // canonical EWAH output (device)
+    uint64_t* out_n;      // output length (device)
+    TileState* state;     // tiles entries
+    uint64_t cap;         // output capacity in words
+    uint32_t N, T, U, tiles;
+    uint32_t tail_bits;   // n_bits % 64
+    uint32_t variant;     // VAR_* flags
+};
+
+// Variant flags (kernel strategy knobs; results never depend on them).
+enum : uint32_t {
+    VAR_DENSE = 1u << 0,        // whole-tile dirty runs through the register CSA tree
+    VAR_WALK_SHIFT = 8,         // bits 8..15: max compressed words for a one-lane walk
+    VAR_LITWALK_SHIFT = 16,     // bits 16..23: max literal-block words for a one-lane loop
+    VAR_EXPLICIT = 1u << 31,    // set in every explicit code so that 0 can mean "default"
+};
+
+__host__ __device__ inline uint32_t var_make(bool dense, uint32_t walk, uint32_t litwalk) {
+    return VAR_EXPLICIT | (dense ? VAR_DENSE : 0u) | ((walk & 255u) << VAR_WALK_SHIFT) |
+           ((litwalk & 255u) << VAR_LITWALK_SHIFT);
+}
+
+__host__ __device__ inline int planes_for(uint32_t n) {
+    int p = 1;
+    while (p < MAXP && (n >> p) != 0) ++p;
+    return p;
+}
+
+// LDS bytes needed by the tile routine for a query with N inputs.
+__host__ __device__ inline size_t tile_smem_bytes(uint32_t N) {
+    size_t P = (size_t)planes_for(N);
+    size_t b = P * TW * 8;                 // count planes
+    b += (TW + 8) * 4;                     // one-fill difference array (+ pad)
+    b += 2 * BLOCK * 16;                   // cooperative items (two per input)
+    b += (2 * BLOCK + 8) * 4;              // window prefix
+    b += BLOCK * 8;                        // dense row pointers
+    b += 64 * 4;                           // misc counters / scan scratch
+    b += NWAVES * 64;                      // chain flags
+    return b;
+}
+
+// Host-side launchers (defined with the kernels).
+hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* ticket, uint32_t epoch, uint32_t* err,
+                        hipStream_t s);
+hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, uint32_t nq, const BitmapDev* table, uint32_t* work,
+                        const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid, size_t smem, hipStream_t s);
+hipError_t launch_bump(uint32_t* epoch, hipStream_t s);
+hipError_t launch_zero_len(uint64_t* out_n, hipStream_t s);
+hipError_t set_smem_limits(size_t max_bytes);
+
+}  // namespace ewt

@@ -1,0 +1,228 @@
+"""Thin Python binding of libewahthr.so (include/ewahthr.h): argument marshalling only.
+
+Every step of the query runs in the HIP kernels of the library; PyTorch only
+provides device memory (tensors whose data_ptr is handed over) and streams.
+Names follow the C ABI without the `ewah_` prefix.  If the native library is
+missing this module raises on import: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libewahthr.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+
+_L = ctypes.CDLL(LIB_PATH)
+_vp, _u32, _u64, _i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+
+OK, EINVAL, EFORMAT, ENOMEM, ENOSPC, EDEVICE = 0, -1, -2, -3, -4, -5
+
+
+class View(ctypes.Structure):
+    _fields_ = [("words", _vp), ("n_words", _u64), ("n_bits", _u64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, _u64) for n in ("n_bits", "n_words", "n_markers", "n_literals", "one_fill_words",
+                                    "popcount", "run_count", "index_bytes")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class Query(ctypes.Structure):
+    _fields_ = [("idx", _vp), ("n", _u32), ("T", _u32), ("out_words_dev", _vp), ("out_cap", _u64),
+                ("out_n_words_dev", _vp), ("variant", _u32)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("grid", _u32), ("use_graph", _i32)]
+
+
+def _sig(name, res, args):
+    f = getattr(_L, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_init = _sig("ewah_init", _i32, [_i32])
+_last_error = _sig("ewah_last_error", ctypes.c_char_p, [])
+_register_many = _sig("ewah_register_many", _i32, [ctypes.POINTER(View), _u32, _i32, ctypes.POINTER(_vp)])
+_release = _sig("ewah_release", None, [_vp])
+_get_stats = _sig("ewah_get_stats", _i32, [_vp, ctypes.POINTER(Stats)])
+_device_words = _sig("ewah_device_words", _vp, [_vp])
+_output_bound = _sig("ewah_output_bound", _u64, [_u64, _u64])
+_threshold_v = _sig("ewah_threshold_v", _i32, [ctypes.POINTER(_vp), _u32, _u32, _vp, _u64, _vp, _u32, _vp])
+_variant_code = _sig("ewah_variant_code", _u32, [_i32, _u32, _u32])
+_default_variant = _sig("ewah_default_variant", _u32, [])
+_batch_plan = _sig("ewah_batch_plan", _i32, [ctypes.POINTER(_vp), _u32, ctypes.POINTER(Query), _u32,
+                                             ctypes.POINTER(BatchConfig), ctypes.POINTER(_vp)])
+_batch_run = _sig("ewah_batch_run", _i32, [_vp, _vp])
+_batch_set_variants = _sig("ewah_batch_set_variants", _i32, [_vp, _vp])
+_batch_set_grid = _sig("ewah_batch_set_grid", _i32, [_vp, _u32])
+_batch_free = _sig("ewah_batch_free", None, [_vp])
+_device_errors = _sig("ewah_device_errors", _i32, [ctypes.POINTER(_u32)])
+_num_cus = _sig("ewah_num_cus", _u32, [])
+
+EXPORTED = ["ewah_init", "ewah_last_error", "ewah_register", "ewah_register_many", "ewah_release",
+            "ewah_get_stats", "ewah_device_words", "ewah_output_bound", "ewah_threshold", "ewah_threshold_v",
+            "ewah_variant_code", "ewah_default_variant", "ewah_batch_plan", "ewah_batch_run",
+            "ewah_batch_set_variants", "ewah_batch_set_grid", "ewah_batch_free", "ewah_device_errors",
+            "ewah_num_cus"]
+
+
+class EwahError(RuntimeError):
+    def __init__(self, code, where):
+        msg = _last_error().decode(errors="replace")
+        super().__init__(f"{where}: status {code}: {msg}")
+        self.code = code
+
+
+def _check(code, where):
+    if code != OK:
+        raise EwahError(code, where)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)   # torch.cuda.Stream: a hipStream_t on ROCm
+
+
+def init(device: int = 0):
+    _check(_init(device), "init")
+
+
+def num_cus() -> int:
+    return int(_num_cus())
+
+
+def output_bound(n_bits: int, sum_input_words: int) -> int:
+    return int(_output_bound(n_bits, sum_input_words))
+
+
+def variant_code(dense: bool, walk: int, litwalk: int) -> int:
+    return int(_variant_code(1 if dense else 0, walk, litwalk))
+
+
+def default_variant() -> int:
+    return int(_default_variant())
+
+
+class Bitmap:
+    """A registered bitmap (library-owned device copy + indexes)."""
+    __slots__ = ("_h", "n_bits", "n_words")
+
+    def __init__(self, handle, n_bits, n_words):
+        self._h = handle
+        self.n_bits = n_bits
+        self.n_words = n_words
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(_get_stats(self._h, ctypes.byref(s)), "get_stats")
+        return s.as_dict()
+
+    def device_words_ptr(self) -> int:
+        return int(_device_words(self._h))
+
+    def release(self):
+        if self._h:
+            _release(self._h)
+            self._h = None
+
+
+def register_many(streams, n_bits: int, on_device: bool = False) -> list:
+    """Register EWAH streams (np.uint64 host arrays, or device pointers with on_device)."""
+    count = len(streams)
+    if count == 0:
+        return []
+    views = (View * count)()
+    keep = []
+    for i, s in enumerate(streams):
+        if on_device:
+            ptr, n = s
+        else:
+            a = np.ascontiguousarray(np.asarray(s, dtype=np.uint64))
+            keep.append(a)
+            ptr, n = (a.ctypes.data if len(a) else None), len(a)
+        views[i].words = ptr
+        views[i].n_words = n
+        views[i].n_bits = n_bits
+    outs = (_vp * count)()
+    _check(_register_many(views, count, 1 if on_device else 0, outs), "register_many")
+    res = []
+    for i in range(count):
+        res.append(Bitmap(outs[i], n_bits, views[i].n_words))
+    return res
+
+
+def register(stream, n_bits: int) -> Bitmap:
+    return register_many([stream], n_bits)[0]
+
+
+def threshold(bitmaps, T: int, out_words_ptr: int, out_cap: int, out_n_ptr: int, stream=None, variant: int = 0):
+    """Enqueue one T-of-N query; outputs are device pointers (e.g. tensor.data_ptr())."""
+    n = len(bitmaps)
+    arr = (_vp * max(n, 1))(*[b.handle for b in bitmaps])
+    _check(_threshold_v(arr, n, T, out_words_ptr, out_cap, out_n_ptr, variant, _stream_ptr(stream)), "threshold")
+
+
+class Batch:
+    """A planned batch of queries run by one persistent, optionally graph-captured launch."""
+
+    def __init__(self, pool, queries, out_ptrs, out_caps, out_n_ptrs, variants=None, grid=0, use_graph=True):
+        nq = len(queries)
+        pool_arr = (_vp * len(pool))(*[b.handle for b in pool])
+        qs = (Query * nq)()
+        self._idx = []
+        for i, (idx, T) in enumerate(queries):
+            a = np.ascontiguousarray(np.asarray(idx, dtype=np.uint32))
+            self._idx.append(a)
+            qs[i].idx = a.ctypes.data
+            qs[i].n = len(a)
+            qs[i].T = T
+            qs[i].out_words_dev = out_ptrs[i]
+            qs[i].out_cap = out_caps[i]
+            qs[i].out_n_words_dev = out_n_ptrs[i]
+            qs[i].variant = 0 if variants is None else int(variants[i])
+        cfg = BatchConfig(grid, 1 if use_graph else 0)
+        h = _vp()
+        _check(_batch_plan(pool_arr, len(pool), qs, nq, ctypes.byref(cfg), ctypes.byref(h)), "batch_plan")
+        self._h = h
+        self.nq = nq
+
+    def run(self, stream=None):
+        _check(_batch_run(self._h, _stream_ptr(stream)), "batch_run")
+
+    def set_variants(self, variants):
+        a = np.ascontiguousarray(np.asarray(variants, dtype=np.uint32))
+        assert len(a) == self.nq
+        _check(_batch_set_variants(self._h, a.ctypes.data), "batch_set_variants")
+
+    def set_grid(self, grid: int):
+        _check(_batch_set_grid(self._h, grid), "batch_set_grid")
+
+    def free(self):
+        if self._h:
+            _batch_free(self._h)
+            self._h = None
+
+
+def device_errors() -> int:
+    v = _u32(0)
+    _check(_device_errors(ctypes.byref(v)), "device_errors")
+    return int(v.value)
