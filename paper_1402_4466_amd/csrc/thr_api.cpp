@@ -82,7 +82,9 @@ ewah_status ensure_ready() {
 // ----------------------------------------------------------- index builder
 
 struct Built {
-    std::vector<uint2> loc, skip;
+    std::vector<uint2> loc;
+    std::vector<uint64_t> mmask;
+    std::vector<uint32_t> mpos;
     ewah_stats st{};
 };
 
@@ -96,7 +98,8 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
     const uint64_t tiles = (U + TW - 1) / TW;
     const uint64_t nchunks = (nw + CHUNK - 1) / CHUNK;
     b.loc.assign(tiles + 1, make_uint2(0, 0));
-    b.skip.assign(nchunks, make_uint2(0, 64));
+    b.mmask.assign(nchunks, 0);
+    b.mpos.assign(nchunks, 0);
     const uint64_t tailmask = (n_bits % 64) ? ((1ull << (n_bits % 64)) - 1) : ~0ull;
     ewah_stats& st = b.st;
     st = ewah_stats{};
@@ -121,8 +124,8 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
         if (K > U - u - L) return fail(EWAH_EFORMAT, "marker at word " + std::to_string(p) + ": literal run past the end");
         st.n_markers++;
         const uint64_t c = p / CHUNK;
-        if (b.skip[c].y == 64) b.skip[c].y = (uint32_t)(p - c * CHUNK);
-        if (p % CHUNK == 0) b.skip[c].x = (uint32_t)u;
+        b.mmask[c] |= 1ull << (p - c * CHUNK);
+        if (p % CHUNK == 0) b.mpos[c] = (uint32_t)u;
         if (L + K > 0) {
             for (uint64_t t = (u + TW - 1) / TW; t * TW < u + L + K && t < tiles; ++t) b.loc[t] = make_uint2((uint32_t)p, (uint32_t)u);
         }
@@ -142,7 +145,7 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
         }
         for (uint64_t i = 0; i < K; ++i) {
             const uint64_t q = p + 1 + i, pos = u + L + i;
-            if (q % CHUNK == 0) b.skip[q / CHUNK].x = (uint32_t)pos;
+            if (q % CHUNK == 0) b.mpos[q / CHUNK] = (uint32_t)pos;
             uint64_t v = w[q];
             const uint64_t nbits = (pos == U - 1) ? (n_bits - (U - 1) * 64) : 64;
             if (pos == U - 1) v &= tailmask;
@@ -155,7 +158,7 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
     }
     if (u != U) return fail(EWAH_EFORMAT, "stream covers " + std::to_string(u) + " words, expected " + std::to_string(U));
     if (tiles) b.loc[tiles] = make_uint2((uint32_t)nw, (uint32_t)U);
-    st.index_bytes = (b.loc.size() + b.skip.size()) * sizeof(uint2);
+    st.index_bytes = b.loc.size() * sizeof(uint2) + b.mmask.size() * 12;
     return EWAH_OK;
 }
 
@@ -288,12 +291,11 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
         st = build_index(w, v[i].n_words, v[i].n_bits, built[i]);
         if (st) return fail(st, "bitmap " + std::to_string(i) + ": " + g_err);
     }
-    // one device arena: [words padded to CHUNK | skip | loc] per bitmap
+    // one device arena: [words padded to CHUNK | marker masks | chunk positions | loc] per bitmap
     std::vector<size_t> off(count + 1, 0);
     for (uint32_t i = 0; i < count; ++i) {
-        size_t nch = built[i].skip.size();
-        size_t sz = align256(std::max<size_t>(nch, 1) * CHUNK * 8) + align256(std::max<size_t>(nch, 1) * 8) +
-                    align256(built[i].loc.size() * 8);
+        size_t nch = std::max<size_t>(built[i].mmask.size(), 1);
+        size_t sz = align256(nch * CHUNK * 8) + align256(nch * 8) + align256(nch * 4) + align256(built[i].loc.size() * 8);
         off[i + 1] = off[i] + sz;
     }
     Arena* arena = new Arena();
@@ -305,18 +307,24 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
     HIPCHK(hipMemset(arena->d, 0, off[count]));
     for (uint32_t i = 0; i < count; ++i) {
         char* base = (char*)arena->d + off[i];
-        size_t nch = std::max<size_t>(built[i].skip.size(), 1);
+        size_t nch = std::max<size_t>(built[i].mmask.size(), 1);
         uint64_t* dw = (uint64_t*)base;
-        uint2* dskip = (uint2*)(base + align256(nch * CHUNK * 8));
-        uint2* dloc = (uint2*)(base + align256(nch * CHUNK * 8) + align256(nch * 8));
+        uint64_t* dmask = (uint64_t*)(base + align256(nch * CHUNK * 8));
+        uint32_t* dpos = (uint32_t*)(base + align256(nch * CHUNK * 8) + align256(nch * 8));
+        uint2* dloc = (uint2*)(base + align256(nch * CHUNK * 8) + align256(nch * 8) + align256(nch * 4));
         const uint64_t* src = on_device ? host[i].data() : v[i].words;
         if (v[i].n_words) HIPCHK(hipMemcpy(dw, src, v[i].n_words * 8, hipMemcpyHostToDevice));
-        if (!built[i].skip.empty()) HIPCHK(hipMemcpy(dskip, built[i].skip.data(), built[i].skip.size() * 8, hipMemcpyHostToDevice));
+        if (!built[i].mmask.empty()) {
+            HIPCHK(hipMemcpy(dmask, built[i].mmask.data(), built[i].mmask.size() * 8, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(dpos, built[i].mpos.data(), built[i].mpos.size() * 4, hipMemcpyHostToDevice));
+        }
         HIPCHK(hipMemcpy(dloc, built[i].loc.data(), built[i].loc.size() * 8, hipMemcpyHostToDevice));
         ewah_bitmap* b = new ewah_bitmap();
         b->dev.words = dw;
         b->dev.loc = dloc;
-        b->dev.skip = dskip;
+        b->dev.mmask = dmask;
+        b->dev.mpos = dpos;
+        b->dev.pad = 0;
         b->dev.n_words = (uint32_t)v[i].n_words;
         b->dev.U = (uint32_t)((v[i].n_bits + 63) / 64);
         b->stats = built[i].st;

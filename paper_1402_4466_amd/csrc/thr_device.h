@@ -15,10 +15,11 @@
 //      fewer than T non-empty inputs -> all zeros, else count;
 //   3. decode: short segments are walked by one lane; long ones are split into
 //      64-word windows aligned to the compressed stream, each decoded by one
-//      wavefront: a skip-index entry gives the first marker of the window, the
-//      marker chain (next = p + 1 + K) is resolved by pointer doubling across the
-//      wavefront, and a wavefront prefix scan of (L + K) over the markers gives
-//      every word's uncompressed position;
+//      wavefront: the skip index gives the window's marker mask (built at
+//      registration by following the marker chain next = p + 1 + K) and the
+//      position of its first word, and a wavefront prefix scan of the words'
+//      spans (L for a marker, 1 for a dirty word) gives every word's
+//      uncompressed position;
 //   4. count: dirty words are added into a bit-sliced per-row counter in LDS
 //      (planes A_1..A_P, least significant first, as in the bit-sliced index of
 //      Section 5.3.1) with an atomic ripple-carry add (ScanCount with bit-sliced
@@ -42,17 +43,19 @@ namespace ewt {
 constexpr int TW = 1024;          // tile width in uncompressed 64-bit words (= locator granularity)
 constexpr int BLOCK = 1024;       // threads per workgroup (one per word position of a tile)
 constexpr int NWAVES = BLOCK / 64;
-constexpr int CHUNK = 64;         // compressed words per skip-index entry
+constexpr int CHUNK = 64;         // compressed words per skip-index entry (one wavefront)
 constexpr int MAXP = 12;          // bit planes: inputs per query < 2^12 (LDS budget)
 constexpr uint32_t MAXN = (1u << MAXP) - 1;
 
-// Registered bitmap as seen by the kernels (32 bytes).
+// Registered bitmap as seen by the kernels (48 bytes).
 struct BitmapDev {
     const uint64_t* words;   // EWAH stream, zero-padded to a multiple of CHUNK words
     const uint2* loc;        // tiles + 1 entries: (marker index, its run start) covering tile start
-    const uint2* skip;       // one per CHUNK words: (position of the chunk's first word, first marker offset or 64)
+    const uint64_t* mmask;   // per CHUNK words: bit j set iff word 64c + j is a marker
+    const uint32_t* mpos;    // per CHUNK words: uncompressed position where word 64c's coverage starts
     uint32_t n_words;
     uint32_t U;              // uncompressed words
+    uint64_t pad;
 };
 
 // Associative run-structure aggregate of a range of output words (see encode step).

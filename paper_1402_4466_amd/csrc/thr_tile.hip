@@ -153,53 +153,114 @@ __device__ __forceinline__ void walk_body(const uint64_t* __restrict__ words, ui
     }
 }
 
-// Decode one 64-word window (chunk c) of a compressed stream with one wavefront.
-// Returns for this lane: whether its word is a marker, and its position (literal) or run start (marker).
-__device__ __forceinline__ void decode_window(uint64_t v, uint2 sk, volatile uint8_t* wf, bool& is_marker,
-                                              uint32_t& pos) {
+// Inclusive prefix sum across the 64 lanes with DPP row shifts and row
+// broadcasts (no LDS traffic): shifts by 1, 2, 4, 8 inside each row of 16
+// lanes, then lane 15 of each row is added to the next row and lane 31 to the
+// upper two rows.
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return v;
+}
+
+// Decode one 64-word window (chunk c) of a compressed stream with one
+// wavefront.  M (bit j = word 64c + j is a marker) and uw0 (position where
+// word 64c's coverage starts) come from the skip index.  A marker covers L
+// fill words and is followed by its K dirty words, so with span = L for a
+// marker and 1 for a dirty word, each word starts at uw0 + (exclusive scan of
+// the spans): the run start for a marker, the position for a dirty word.
+__device__ __forceinline__ uint32_t decode_window(uint64_t v, uint64_t M, uint32_t uw0, bool& is_marker) {
     const int lane = __lane_id();
-    const uint32_t uw0 = sk.x, m0 = sk.y;
-    uint64_t M = 0;
-    if (m0 < 64u) {
-        // next marker offset if this word were a marker, 64 = outside the window
-        uint32_t K = (uint32_t)(v >> 33);
-        uint32_t nx = (uint32_t)lane + 1u + K;
-        uint32_t J0 = nx > 64u ? 64u : nx;
-        // pointer doubling: J_r = next^(2^r)
-        uint32_t J1 = __shfl(J0, (int)(J0 & 63u), 64); J1 = J0 < 64u ? J1 : 64u;
-        uint32_t J2 = __shfl(J1, (int)(J1 & 63u), 64); J2 = J1 < 64u ? J2 : 64u;
-        uint32_t J3 = __shfl(J2, (int)(J2 & 63u), 64); J3 = J2 < 64u ? J3 : 64u;
-        uint32_t J4 = __shfl(J3, (int)(J3 & 63u), 64); J4 = J3 < 64u ? J4 : 64u;
-        uint32_t J5 = __shfl(J4, (int)(J4 & 63u), 64); J5 = J4 < 64u ? J5 : 64u;
-        // chain members from m0: {c_0} -> + c_32 -> + c_16, c_48 -> ... -> all
-        wf[lane] = (uint32_t)lane == m0 ? 1 : 0;
-        __builtin_amdgcn_wave_barrier();
-        uint32_t Js[6] = {J0, J1, J2, J3, J4, J5};
-#pragma unroll
-        for (int r = 5; r >= 0; --r) {
-            uint8_t in = wf[lane];
-            __builtin_amdgcn_wave_barrier();
-            if (in && Js[r] < 64u) wf[Js[r]] = 1;
-            __builtin_amdgcn_wave_barrier();
-        }
-        bool im = wf[lane] != 0;
-        __builtin_amdgcn_wave_barrier();
-        M = __ballot(im);
-    }
     is_marker = (M >> lane) & 1ull;
-    uint32_t L = (uint32_t)((v >> 1) & 0xFFFFFFFFu), K = (uint32_t)(v >> 33);
-    uint32_t len = is_marker ? L + K : 0u;
-    uint32_t ex = wave_incl_scan(len) - len;
-    uint32_t um = uw0 + m0 + ex;                 // run start (meaningful for marker lanes)
-    uint64_t below = lane == 0 ? 0ull : (M & (~0ull >> (64 - lane)));
-    int owner = below ? 63 - __clzll((long long)below) : -1;
-    uint32_t ob = __shfl(um + L, owner < 0 ? 0 : owner, 64);
-    pos = is_marker ? um : (owner < 0 ? uw0 + (uint32_t)lane : ob + (uint32_t)(lane - owner - 1));
+    const uint32_t span = is_marker ? (uint32_t)((v >> 1) & 0xFFFFFFFFu) : 1u;
+    return uw0 + wave_incl_scan_dpp(span) - span;
+}
+
+// Exclusive prefix of the run-structure aggregate over tiles [0, t), by
+// decoupled look-back read 64 predecessors at a time: lane i looks at tile
+// base - i; the nearest tile that has published its inclusive prefix ends the
+// search, and the local aggregates of the tiles after it are reduced across
+// the wavefront (the aggregate is associative).  Called by one whole wavefront.
+__device__ Agg lookback(TileState* st, int t, uint32_t epoch, uint32_t* err) {
+    const int lane = __lane_id();
+    bool acc_empty = true;
+    Agg acc;
+    acc.n = 0; acc.lh_pos = 0; acc.lh_out = 0; acc.bits = 0;
+    int base = t - 1;
+    uint32_t spins = 0;
+    while (true) {
+        const int j = base - lane;
+        uint32_t fi = 0, fl = 0;
+        if (j >= 0) {
+            fi = __hip_atomic_load(&st[j].flag_incl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            fl = __hip_atomic_load(&st[j].flag_local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const bool inc = j >= 0 && fi == epoch;
+        const bool loc = j >= 0 && fl == epoch;
+        const uint64_t incm = __ballot(inc);
+        const int linc = incm ? (__ffsll((long long)incm) - 1) : 64;
+        const bool need = j >= 0 && lane <= linc;
+        const bool ok = !need || inc || loc;
+        if (__ballot(!ok) != 0ull) {
+            if (++spins > (1u << 22)) {
+                if (lane == 0) atomicOr(err, 1u);
+                return acc;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        Agg v;
+        v.n = 0; v.lh_pos = 0; v.lh_out = 0; v.bits = 0;
+        if (need) v = agg_load(lane == linc ? &st[j].incl : &st[j].local);
+        bool empty = !need;
+        // tree reduction: lane i + d holds the lower (earlier) tiles
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            Agg o;
+            o.n = __shfl_down(v.n, d, 64);
+            o.lh_pos = __shfl_down(v.lh_pos, d, 64);
+            o.lh_out = __shfl_down(v.lh_out, d, 64);
+            o.bits = __shfl_down(v.bits, d, 64);
+            const bool oe = __shfl_down((int)empty, d, 64) != 0 || lane + d >= 64;
+            if ((lane & (2 * d - 1)) == 0 && !oe) {
+                if (empty) { v = o; empty = false; }
+                else v = agg_combine(o, v, (uint32_t)(base - lane - d + 1) * (uint32_t)TW);
+            }
+        }
+        Agg R;
+        R.n = __shfl(v.n, 0, 64);
+        R.lh_pos = __shfl(v.lh_pos, 0, 64);
+        R.lh_out = __shfl(v.lh_out, 0, 64);
+        R.bits = __shfl(v.bits, 0, 64);
+        acc = acc_empty ? R : agg_combine(R, acc, (uint32_t)(base + 1) * (uint32_t)TW);
+        acc_empty = false;
+        if (linc < 64) return acc;
+        base -= 64;
+        if (base < 0) {   // tile 0 always publishes an inclusive value: cannot get here
+            if (lane == 0) atomicOr(err, 2u);
+            return acc;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- the tile
 
 // Misc LDS slots.
+constexpr int WIN_BATCH = 8;   // windows grabbed per wavefront at a time
+
+#ifdef EWT_PHASE_TIMING
+// Debug builds only: per-tile timestamps of the phase boundaries.
+__device__ uint64_t* ewt_phase_buf;
+#define EWT_PHASE(k) do { if (threadIdx.x == 0 && ewt_phase_buf) ewt_phase_buf[(size_t)t * 8 + (k)] = wall_clock64(); } while (0)
+#else
+#define EWT_PHASE(k) do { } while (0)
+#endif
+
 enum { M_NITEMS = 0, M_NDENSE, M_WINCTR, M_NWIN, M_ONEFULL, M_NONZERO, M_TMP = 8, M_X = 32, M_TOT = 40 };
 
 __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ table, uint32_t t,
@@ -220,9 +281,9 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     uint32_t* winp = (uint32_t*)(items + 2 * BLOCK);
     const uint64_t** dense = (const uint64_t**)(winp + 2 * BLOCK + 8);
     uint32_t* misc = (uint32_t*)(dense + BLOCK);
-    volatile uint8_t* wflags = (volatile uint8_t*)(misc + 64) + wave * 64;
     (void)nb;
 
+    EWT_PHASE(0);
     for (int i = tid; i < P * TW; i += BLOCK) planes[i] = 0;
     for (int i = tid; i < TW + 8; i += BLOCK) diff[i] = 0;
     if (tid < 8) misc[tid] = 0;
@@ -243,6 +304,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         }
     }
     __syncthreads();
+    EWT_PHASE(1);
     const uint32_t mode = trivial ? (T == 0 ? 1u : 2u)
                                   : (misc[M_ONEFULL] >= T ? 1u : (misc[M_NONZERO] < T ? 2u : 0u));
 
@@ -276,6 +338,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                 }
             }
             __syncthreads();
+            EWT_PHASE(2);
             // window prefix over the cooperative items (two per thread)
             const uint32_t n_items = misc[M_NITEMS];
             uint32_t w2[2] = {0u, 0u};
@@ -294,48 +357,114 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             if (tid == 0) { misc[M_NWIN] = tot; misc[M_WINCTR] = 0; }
             __syncthreads();
 
-            // cooperative windows: one wavefront per 64 compressed words
+            // cooperative windows: one wavefront per 64 compressed words, WIN_BATCH
+            // windows per grab, all loads issued before any decoding and the
+            // ripple adds of the batch interleaved
             const uint32_t total_w = misc[M_NWIN];
             while (true) {
-                uint32_t w = 0;
-                if (lane == 0) w = atomicAdd(&misc[M_WINCTR], 1u);
-                w = __shfl(w, 0, 64);
-                if (w >= total_w) break;
-                uint32_t lo = 0, hi = n_items - 1;       // largest i with winp[i] <= w
+                uint32_t w0 = 0;
+                if (lane == 0) w0 = atomicAdd(&misc[M_WINCTR], (uint32_t)WIN_BATCH);
+                w0 = __shfl(w0, 0, 64);
+                if (w0 >= total_w) break;
+                uint32_t lo = 0, hi = n_items - 1;       // largest i with winp[i] <= w0
                 while (lo < hi) {
                     uint32_t mid = (lo + hi + 1) >> 1;
-                    if (winp[mid] <= w) lo = mid; else hi = mid - 1;
+                    if (winp[mid] <= w0) lo = mid; else hi = mid - 1;
                 }
-                uint4 it = items[lo];
-                uint32_t wi = w - winp[lo];
-                const BitmapDev& B = table[it.x];
-                if (it.w & 0x80000000u) {
-                    uint32_t la = it.w & 0x7FFFFFFFu;
-                    uint32_t qv = it.y + wi * 64u + (uint32_t)lane;
-                    if (qv < it.z) ripple_add(planes, la + (qv - it.y) - tS, B.words[qv], P);
-                } else {
-                    uint32_t c = (it.y >> 6) + wi;
-                    uint32_t qv = c * 64u + (uint32_t)lane;
-                    uint64_t v = B.words[qv];
-                    uint2 sk = B.skip[c];
-                    bool im;
-                    uint32_t pos;
-                    decode_window(v, sk, wflags, im, pos);
-                    if (qv >= it.y && qv < it.z) {
-                        if (im) {
-                            if (v & 1ull) {
-                                uint32_t L = (uint32_t)((v >> 1) & 0xFFFFFFFFu);
-                                uint32_t fa = max(pos, tS), fb = min(pos + L, tE);
-                                if (fa < fb) { atomicAdd(&diff[fa - tS], 1); atomicAdd(&diff[fb - tS], -1); }
-                            }
-                        } else if (pos >= tS && pos < tE) {
-                            ripple_add(planes, pos - tS, v, P);
+                lo = __builtin_amdgcn_readfirstlane(lo);
+                uint32_t wi = w0 - winp[lo];
+                uint32_t lo_n = ((lo + 1 < n_items) ? winp[lo + 1] : total_w) - winp[lo];
+                uint64_t vs[WIN_BATCH];
+                uint64_t ms[WIN_BATCH];
+                uint32_t ps[WIN_BATCH];
+                uint4 its[WIN_BATCH];
+                uint32_t qs[WIN_BATCH];
+#pragma unroll
+                for (int g = 0; g < WIN_BATCH; ++g) {
+                    if (g > 0) {
+                        if (wi + 1u >= lo_n && lo + 1 < n_items) {
+                            ++lo;
+                            wi = 0;
+                            lo_n = ((lo + 1 < n_items) ? winp[lo + 1] : total_w) - winp[lo];
+                        } else {
+                            ++wi;
                         }
                     }
+                    uint4 it = items[lo];
+                    it.x = __builtin_amdgcn_readfirstlane(it.x);
+                    it.y = __builtin_amdgcn_readfirstlane(it.y);
+                    it.z = __builtin_amdgcn_readfirstlane(it.z);
+                    it.w = __builtin_amdgcn_readfirstlane(it.w);
+                    its[g] = it;
+                    vs[g] = 0;
+                    ms[g] = 0;
+                    ps[g] = 0;
+                    qs[g] = 0;
+                    if (w0 + (uint32_t)g < total_w) {
+                        const BitmapDev* B = &table[it.x];
+                        if (it.w & 0x80000000u) {
+                            const uint32_t qv = it.y + wi * 64u + (uint32_t)lane;
+                            qs[g] = qv;
+                            if (qv < it.z) vs[g] = __builtin_nontemporal_load(B->words + qv);
+                        } else {
+                            const uint32_t c = (it.y >> 6) + wi;
+                            const uint32_t qv = c * 64u + (uint32_t)lane;
+                            qs[g] = qv;
+                            vs[g] = __builtin_nontemporal_load(B->words + qv);
+                            const uint64_t mk = B->mmask[c];
+                            // readfirstlane returns int: widen through uint32_t, never sign-extend
+                            ms[g] = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(mk >> 32)) << 32) |
+                                    (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)mk);
+                            ps[g] = __builtin_amdgcn_readfirstlane(B->mpos[c]);
+                        }
+                    }
+                }
+                // decode: position of every dirty word in the tile (or no add)
+                uint32_t rp[WIN_BATCH];
+#pragma unroll
+                for (int g = 0; g < WIN_BATCH; ++g) {
+                    const uint4 it = its[g];
+                    const uint32_t qv = qs[g];
+                    uint64_t v = vs[g];
+                    uint32_t r = 0;
+                    if (w0 + (uint32_t)g >= total_w) {
+                        v = 0;
+                    } else if (it.w & 0x80000000u) {
+                        if (qv < it.z) r = (it.w & 0x7FFFFFFFu) + (qv - it.y) - tS;
+                        else v = 0;
+                    } else {
+                        bool im;
+                        const uint32_t pos = decode_window(v, ms[g], ps[g], im);
+                        const bool in = qv >= it.y && qv < it.z;
+                        if (in && im && (v & 1ull)) {
+                            const uint32_t L = (uint32_t)((v >> 1) & 0xFFFFFFFFu);
+                            const uint32_t fa = max(pos, tS), fb = min(pos + L, tE);
+                            if (fa < fb) { atomicAdd(&diff[fa - tS], 1); atomicAdd(&diff[fb - tS], -1); }
+                        }
+                        if (in && !im && pos >= tS && pos < tE) r = pos - tS;
+                        else v = 0;
+                    }
+                    vs[g] = v;
+                    rp[g] = r;
+                }
+                // interleaved ripple-carry adds of the batch
+                for (int p = 0; p < P; ++p) {
+                    uint64_t any = 0;
+#pragma unroll
+                    for (int g = 0; g < WIN_BATCH; ++g) {
+                        if (vs[g]) {
+                            const uint64_t old = atomicXor((unsigned long long*)&planes[p * TW + rp[g]],
+                                                           (unsigned long long)vs[g]);
+                            vs[g] &= old;
+                        }
+                        any |= vs[g];
+                    }
+                    if (!__any(any != 0)) break;
                 }
             }
             __syncthreads();
 
+            EWT_PHASE(3);
             // dense rows: Harley-Seal carry-save-adder tree, one lane per word position
             const uint32_t n_dense = misc[M_NDENSE];
             if (n_dense && (uint32_t)tid < nPos) {
@@ -389,6 +518,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         }
     }
 
+    EWT_PHASE(4);
     // ---- compare: count >= T - k1 per row, bit-sliced
     uint32_t k1tot;
     int32_t dv = tid < TW ? diff[tid] : 0;
@@ -415,6 +545,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         if (tS + (uint32_t)tid == U - 1u && q.tail_bits) o &= (1ull << q.tail_bits) - 1ull;
     }
     __syncthreads();   // planes are reused below
+    EWT_PHASE(5);
 
     // ---- encode: canonical EWAH by scan-and-compact with decoupled look-back
     uint8_t* clsA = (uint8_t*)smem;                        // TW
@@ -434,7 +565,8 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     if (hl) { hpos[ex_head] = (uint16_t)tid; hout[ex_head] = (uint16_t)ex_emit; }
     __syncthreads();
 
-    if (tid == 0) {
+    if (wave == 0) {
+        // local aggregate of this tile (every lane of wave 0 computes it)
         Agg A;
         A.n = n_local;
         uint32_t bits = (uint32_t)clsA[0] | ((uint32_t)clsA[nPos - 1] << 2);
@@ -452,42 +584,23 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         X.n = 0; X.lh_pos = 0; X.lh_out = 0; X.bits = 3u << 2;
         Agg I = A;
         if (t > 0) {
-            agg_store(&st[t].local, A);
-            __hip_atomic_store(&st[t].flag_local, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            bool acc_empty = true;
-            Agg acc = A;
-            int j = (int)t - 1;
-            uint32_t spins = 0;
-            while (true) {
-                uint32_t fi = __hip_atomic_load(&st[j].flag_incl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (fi == epoch) {
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    Agg Ij = agg_load(&st[j].incl);
-                    X = acc_empty ? Ij : agg_combine(Ij, acc, (uint32_t)(j + 1) * TW);
-                    break;
-                }
-                uint32_t fl = __hip_atomic_load(&st[j].flag_local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (fl == epoch) {
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    Agg Lj = agg_load(&st[j].local);
-                    acc = acc_empty ? Lj : agg_combine(Lj, acc, (uint32_t)(j + 1) * TW);
-                    acc_empty = false;
-                    --j;
-                    if (j < 0) { atomicOr(err, 2u); break; }   // tile 0 always publishes its inclusive value
-                    continue;
-                }
-                if (++spins > (1u << 24)) { atomicOr(err, 1u); break; }
-                __builtin_amdgcn_s_sleep(2);
+            if (lane == 0) {
+                agg_store(&st[t].local, A);
+                __hip_atomic_store(&st[t].flag_local, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
+            X = lookback(st, (int)t, epoch, err);
             I = agg_combine(X, A, tS);
         }
-        agg_store(&st[t].incl, I);
-        __hip_atomic_store(&st[t].flag_incl, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        misc[M_X + 0] = X.n; misc[M_X + 1] = X.lh_pos; misc[M_X + 2] = X.lh_out; misc[M_X + 3] = X.bits;
-        misc[M_TOT] = I.n;
+        if (lane == 0) {
+            agg_store(&st[t].incl, I);
+            __hip_atomic_store(&st[t].flag_incl, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            misc[M_X + 0] = X.n; misc[M_X + 1] = X.lh_pos; misc[M_X + 2] = X.lh_out; misc[M_X + 3] = X.bits;
+            misc[M_TOT] = I.n;
+        }
     }
     __syncthreads();
 
+    EWT_PHASE(6);
     const uint32_t Xn = misc[M_X + 0], Xlh_pos = misc[M_X + 1], Xlh_out = misc[M_X + 2], Xbits = misc[M_X + 3];
     const uint32_t total = misc[M_TOT];
     const uint32_t c0 = clsA[0];
@@ -538,6 +651,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         *q.out_n = total;
     }
     __syncthreads();
+    EWT_PHASE(7);
 }
 
 // ----------------------------------------------------------------- kernels
@@ -623,6 +737,12 @@ hipError_t launch_bump(uint32_t* epoch, hipStream_t s) {
     hipLaunchKernelGGL(bump_epoch_kernel, dim3(1), dim3(1), 0, s, epoch);
     return hipGetLastError();
 }
+
+#ifdef EWT_PHASE_TIMING
+extern "C" int ewt_debug_set_phase_buffer(void* p) {
+    return (int)hipMemcpyToSymbol(HIP_SYMBOL(ewt_phase_buf), &p, sizeof(p));
+}
+#endif
 
 hipError_t launch_zero_len(uint64_t* out_n, hipStream_t s) {
     hipLaunchKernelGGL(zero_len_kernel, dim3(1), dim3(1), 0, s, out_n);

@@ -18,6 +18,13 @@ LIB_PATH = os.path.join(_HERE, "libewahthr.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
 
+# One HIP runtime per process: PyTorch ships its own libamdhip64, so it is
+# loaded first and the library binds to that already-loaded runtime.
+try:
+    import torch  # noqa: F401
+except ImportError:  # a C-ABI user without PyTorch gets the system runtime
+    torch = None
+
 _L = ctypes.CDLL(LIB_PATH)
 _vp, _u32, _u64, _i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
 
