@@ -395,7 +395,7 @@ ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t 
     for (uint32_t i = 0; i < n; ++i) c->h_ids[i] = in[i]->slot;
     HIPCHK(hipMemcpyAsync(c->d_ids, c->h_ids, (size_t)n * 4, hipMemcpyHostToDevice, s));
     HIPCHK(hipEventRecord(c->ev, s));
-    if (++c->epoch == 0) {   // wrapped: clear stale flags
+    if ((++c->epoch & 0xFFFFu) == 0) {   // 16-bit tags wrapped: clear stale states
         HIPCHK(hipMemsetAsync(c->d_state, 0, c->state_cap * sizeof(TileState), s));
         c->epoch = 1;
     }

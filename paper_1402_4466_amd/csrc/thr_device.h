@@ -66,12 +66,16 @@ struct Agg {
     uint32_t bits;     // cf | cl << 2 | has_head << 4 | last head fill bit << 5
 };
 
-struct TileState {        // 48 bytes, one per (query, tile)
-    Agg local;
-    Agg incl;
-    uint32_t flag_local;
-    uint32_t flag_incl;
-    uint32_t pad[2];
+// Published aggregates of one (query, tile), 64 bytes.  Each 64-bit word
+// carries the 16-bit tag of the launch that wrote it in its low bits, so a
+// reader validates every word on its own (no fences: relaxed agent-scope
+// atomics) and words left over from earlier launches are never mistaken for
+// current ones.  Tags cycle through 1..65535; the host clears the states when
+// they wrap.
+struct TileState {
+    uint64_t local[3];    // aggregate of this tile alone
+    uint64_t incl[3];     // aggregate of tiles 0..t
+    uint64_t pad[2];
 };
 
 struct QueryDev {         // 64 bytes

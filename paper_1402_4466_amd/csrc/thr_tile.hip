@@ -75,19 +75,26 @@ __device__ __forceinline__ Agg agg_combine(const Agg& A, const Agg& B, uint32_t 
     return R;
 }
 
-__device__ __forceinline__ void agg_store(Agg* dst, const Agg& a) {
-    __hip_atomic_store(&dst->n, a.n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&dst->lh_pos, a.lh_pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&dst->lh_out, a.lh_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&dst->bits, a.bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Tagged publication: word 0 = tag | n << 16 | bits << 48, word 1 = tag |
+// lh_pos << 16, word 2 = tag | lh_out << 16.
+__device__ __forceinline__ void agg_publish(uint64_t* dst, const Agg& a, uint32_t tag) {
+    const uint64_t t = tag & 0xFFFFu;
+    __hip_atomic_store(&dst[0], t | ((uint64_t)a.n << 16) | ((uint64_t)(a.bits & 63u) << 48), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&dst[1], t | ((uint64_t)a.lh_pos << 16), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&dst[2], t | ((uint64_t)a.lh_out << 16), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ Agg agg_load(Agg* src) {
-    Agg a;
-    a.n = __hip_atomic_load(&src->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a.lh_pos = __hip_atomic_load(&src->lh_pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a.lh_out = __hip_atomic_load(&src->lh_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a.bits = __hip_atomic_load(&src->bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return a;
+// Reads a published aggregate; false if any of its words is not from this launch.
+__device__ __forceinline__ bool agg_fetch(uint64_t* src, uint32_t tag, Agg& a) {
+    const uint64_t w0 = __hip_atomic_load(&src[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t w1 = __hip_atomic_load(&src[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t w2 = __hip_atomic_load(&src[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t t = tag & 0xFFFFu;
+    a.n = (uint32_t)(w0 >> 16);
+    a.bits = (uint32_t)(w0 >> 48) & 63u;
+    a.lh_pos = (uint32_t)(w1 >> 16);
+    a.lh_out = (uint32_t)(w2 >> 16);
+    return (w0 & 0xFFFFu) == t && (w1 & 0xFFFFu) == t && (w2 & 0xFFFFu) == t;
 }
 
 // ------------------------------------------------------------ segment location
@@ -194,13 +201,12 @@ __device__ Agg lookback(TileState* st, int t, uint32_t epoch, uint32_t* err) {
     uint32_t spins = 0;
     while (true) {
         const int j = base - lane;
-        uint32_t fi = 0, fl = 0;
+        Agg vi, vl;
+        bool inc = false, loc = false;
         if (j >= 0) {
-            fi = __hip_atomic_load(&st[j].flag_incl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            fl = __hip_atomic_load(&st[j].flag_local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            inc = agg_fetch(st[j].incl, epoch, vi);
+            loc = agg_fetch(st[j].local, epoch, vl);
         }
-        const bool inc = j >= 0 && fi == epoch;
-        const bool loc = j >= 0 && fl == epoch;
         const uint64_t incm = __ballot(inc);
         const int linc = incm ? (__ffsll((long long)incm) - 1) : 64;
         const bool need = j >= 0 && lane <= linc;
@@ -213,10 +219,9 @@ __device__ Agg lookback(TileState* st, int t, uint32_t epoch, uint32_t* err) {
             __builtin_amdgcn_s_sleep(2);
             continue;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         Agg v;
         v.n = 0; v.lh_pos = 0; v.lh_out = 0; v.bits = 0;
-        if (need) v = agg_load(lane == linc ? &st[j].incl : &st[j].local);
+        if (need) v = (lane == linc) ? vi : vl;
         bool empty = !need;
         // tree reduction: lane i + d holds the lower (earlier) tiles
 #pragma unroll
@@ -584,16 +589,12 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         X.n = 0; X.lh_pos = 0; X.lh_out = 0; X.bits = 3u << 2;
         Agg I = A;
         if (t > 0) {
-            if (lane == 0) {
-                agg_store(&st[t].local, A);
-                __hip_atomic_store(&st[t].flag_local, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            if (lane == 0) agg_publish(st[t].local, A, epoch);
             X = lookback(st, (int)t, epoch, err);
             I = agg_combine(X, A, tS);
         }
         if (lane == 0) {
-            agg_store(&st[t].incl, I);
-            __hip_atomic_store(&st[t].flag_incl, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            agg_publish(st[t].incl, I, epoch);
             misc[M_X + 0] = X.n; misc[M_X + 1] = X.lh_pos; misc[M_X + 2] = X.lh_out; misc[M_X + 3] = X.bits;
             misc[M_TOT] = I.n;
         }
@@ -704,7 +705,14 @@ __global__ __launch_bounds__(BLOCK) void thr_batch_kernel(const QueryDev* __rest
     }
 }
 
-__global__ void bump_epoch_kernel(uint32_t* epoch) { *epoch += 1u; }
+// Next launch tag of a batch; tag 0 (the value of cleared states) is skipped.
+// Every launch of a batch rewrites every tile state, so states older than the
+// previous launch never survive and the 16-bit tag cycle is safe.
+__global__ void bump_epoch_kernel(uint32_t* epoch) {
+    uint32_t e = *epoch + 1u;
+    if ((e & 0xFFFFu) == 0) e += 1u;
+    *epoch = e;
+}
 
 // Output for r = 0 (no words).
 __global__ void zero_len_kernel(uint64_t* out_n) { *out_n = 0; }
