@@ -4,6 +4,20 @@
 
 namespace ewt {
 
+// Pointers read from the device-side bitmap table or query records are
+// generic (flat) pointers; flat accesses may alias LDS, which makes the
+// compiler wait for every load before the next LDS operation.  All global
+// accesses go through the global address space explicitly.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define EWT_GLOBAL __attribute__((address_space(1)))
+#else
+#define EWT_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ EWT_GLOBAL T* gp(T* p) {
+    return (EWT_GLOBAL T*)p;
+}
+
 // ------------------------------------------------------------ wave helpers
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
@@ -77,7 +91,7 @@ __device__ __forceinline__ Agg agg_combine(const Agg& A, const Agg& B, uint32_t 
 
 // Tagged publication: word 0 = tag | n << 16 | bits << 48, word 1 = tag |
 // lh_pos << 16, word 2 = tag | lh_out << 16.
-__device__ __forceinline__ void agg_publish(uint64_t* dst, const Agg& a, uint32_t tag) {
+__device__ __forceinline__ void agg_publish(EWT_GLOBAL uint64_t* dst, const Agg& a, uint32_t tag) {
     const uint64_t t = tag & 0xFFFFu;
     __hip_atomic_store(&dst[0], t | ((uint64_t)a.n << 16) | ((uint64_t)(a.bits & 63u) << 48), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
@@ -85,7 +99,7 @@ __device__ __forceinline__ void agg_publish(uint64_t* dst, const Agg& a, uint32_
     __hip_atomic_store(&dst[2], t | ((uint64_t)a.lh_out << 16), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Reads a published aggregate; false if any of its words is not from this launch.
-__device__ __forceinline__ bool agg_fetch(uint64_t* src, uint32_t tag, Agg& a) {
+__device__ __forceinline__ bool agg_fetch(EWT_GLOBAL uint64_t* src, uint32_t tag, Agg& a) {
     const uint64_t w0 = __hip_atomic_load(&src[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint64_t w1 = __hip_atomic_load(&src[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint64_t w2 = __hip_atomic_load(&src[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -110,9 +124,9 @@ struct Seg {
 
 __device__ __forceinline__ Seg locate(const BitmapDev& B, uint32_t t, uint32_t tS, uint32_t tE, uint32_t tiles) {
     Seg s;
-    uint2 l0 = B.loc[t];
+    const uint2 l0 = gp(B.loc)[t];
     uint32_t pm = l0.x, um = l0.y;
-    uint64_t h = B.words[pm];
+    uint64_t h = gp(B.words)[pm];
     uint32_t f = (uint32_t)(h & 1u), L = (uint32_t)((h >> 1) & 0xFFFFFFFFu), K = (uint32_t)(h >> 33);
     uint32_t fa = max(um, tS), fb = min(um + L, tE);
     s.fa = fa; s.fb = (f && fa < fb) ? fb : fa;
@@ -124,9 +138,9 @@ __device__ __forceinline__ Seg locate(const BitmapDev& B, uint32_t t, uint32_t t
     s.y0 = um + L + K;
     s.be = s.bs;
     if (t + 1 < tiles) {
-        uint2 l1 = B.loc[t + 1];
+        const uint2 l1 = gp(B.loc)[t + 1];
         if (l1.x != pm) {
-            uint64_t h2 = B.words[l1.x];
+            uint64_t h2 = gp(B.words)[l1.x];
             uint32_t L2 = (uint32_t)((h2 >> 1) & 0xFFFFFFFFu), K2 = (uint32_t)(h2 >> 33);
             uint32_t lit_start = l1.y + L2;
             uint32_t inlit = tE > lit_start ? min(K2, tE - lit_start) : 0u;
@@ -141,7 +155,7 @@ __device__ __forceinline__ Seg locate(const BitmapDev& B, uint32_t t, uint32_t t
 }
 
 // One lane walks the markers of [bs, be), starting at a marker whose run starts at y0.
-__device__ __forceinline__ void walk_body(const uint64_t* __restrict__ words, uint32_t bs, uint32_t be,
+__device__ __forceinline__ void walk_body(const EWT_GLOBAL uint64_t* words, uint32_t bs, uint32_t be,
                                           uint32_t y0, uint32_t tS, uint32_t tE, uint64_t* planes,
                                           int32_t* diff, int P) {
     uint32_t p = bs, u = y0;
@@ -192,7 +206,7 @@ __device__ __forceinline__ uint32_t decode_window(uint64_t v, uint64_t M, uint32
 // base - i; the nearest tile that has published its inclusive prefix ends the
 // search, and the local aggregates of the tiles after it are reduced across
 // the wavefront (the aggregate is associative).  Called by one whole wavefront.
-__device__ Agg lookback(TileState* st, int t, uint32_t epoch, uint32_t* err) {
+__device__ Agg lookback(EWT_GLOBAL TileState* st, int t, uint32_t epoch, uint32_t* err) {
     const int lane = __lane_id();
     bool acc_empty = true;
     Agg acc;
@@ -261,7 +275,7 @@ constexpr int WIN_BATCH = 8;   // windows grabbed per wavefront at a time
 #ifdef EWT_PHASE_TIMING
 // Debug builds only: per-tile timestamps of the phase boundaries.
 __device__ uint64_t* ewt_phase_buf;
-#define EWT_PHASE(k) do { if (threadIdx.x == 0 && ewt_phase_buf) ewt_phase_buf[(size_t)t * 8 + (k)] = wall_clock64(); } while (0)
+#define EWT_PHASE(k) do { if (threadIdx.x == 0 && ewt_phase_buf) ewt_phase_buf[(size_t)dbg_slot * 8 + (k)] = wall_clock64(); } while (0)
 #else
 #define EWT_PHASE(k) do { } while (0)
 #endif
@@ -269,7 +283,8 @@ __device__ uint64_t* ewt_phase_buf;
 enum { M_NITEMS = 0, M_NDENSE, M_WINCTR, M_NWIN, M_ONEFULL, M_NONZERO, M_TMP = 8, M_X = 32, M_TOT = 40 };
 
 __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ table, uint32_t t,
-                             uint32_t epoch, unsigned char* smem, uint32_t* err) {
+                             uint32_t epoch, unsigned char* smem, uint32_t* err, uint32_t dbg_slot) {
+    (void)dbg_slot;   // timestamp slot of debug builds
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t N = q.N, T = q.T, U = q.U, tiles = q.tiles;
     const uint32_t tS = t * (uint32_t)TW;
@@ -301,7 +316,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         for (uint32_t kb = 0; kb < N; kb += BLOCK) {
             uint32_t k = kb + (uint32_t)tid;
             if (k < N) {
-                Seg s = locate(table[q.ids[k]], t, tS, tE, tiles);
+                Seg s = locate(gp(table)[gp(q.ids)[k]], t, tS, tE, tiles);
                 if (s.onefull) atomicAdd(&misc[M_ONEFULL], 1u);
                 if (!s.zero) atomicAdd(&misc[M_NONZERO], 1u);
                 if (kb == 0) seg = s;
@@ -318,8 +333,8 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         for (uint32_t kb = 0; kb < N; kb += BLOCK) {
             uint32_t k = kb + (uint32_t)tid;
             if (k < N) {
-                uint32_t slot = q.ids[k];
-                const BitmapDev& B = table[slot];
+                const uint32_t slot = gp(q.ids)[k];
+                const BitmapDev B = gp(table)[slot];
                 Seg s = (kb == 0) ? seg : locate(B, t, tS, tE, tiles);
                 if (s.fa < s.fb) { atomicAdd(&diff[s.fa - tS], 1); atomicAdd(&diff[s.fb - tS], -1); }
                 if (s.cnt) {
@@ -327,7 +342,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                         uint32_t j = atomicAdd(&misc[M_NDENSE], 1u);
                         dense[j] = B.words + s.a_lit;
                     } else if (s.cnt <= litwalk_max) {
-                        for (uint32_t j = 0; j < s.cnt; ++j) ripple_add(planes, s.la - tS + j, B.words[s.a_lit + j], P);
+                        for (uint32_t j = 0; j < s.cnt; ++j) ripple_add(planes, s.la - tS + j, gp(B.words)[s.a_lit + j], P);
                     } else {
                         uint32_t j = atomicAdd(&misc[M_NITEMS], 1u);
                         items[j] = make_uint4(slot, s.a_lit, s.a_lit + s.cnt, s.la | 0x80000000u);
@@ -335,7 +350,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                 }
                 if (s.be > s.bs) {
                     if (s.be - s.bs <= walk_max) {
-                        walk_body(B.words, s.bs, s.be, s.y0, tS, tE, planes, diff, P);
+                        walk_body(gp(B.words), s.bs, s.be, s.y0, tS, tE, planes, diff, P);
                     } else {
                         uint32_t j = atomicAdd(&misc[M_NITEMS], 1u);
                         items[j] = make_uint4(slot, s.bs, s.be, 0u);
@@ -369,7 +384,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             while (true) {
                 uint32_t w0 = 0;
                 if (lane == 0) w0 = atomicAdd(&misc[M_WINCTR], (uint32_t)WIN_BATCH);
-                w0 = __shfl(w0, 0, 64);
+                w0 = __builtin_amdgcn_readfirstlane(__shfl(w0, 0, 64));
                 if (w0 >= total_w) break;
                 uint32_t lo = 0, hi = n_items - 1;       // largest i with winp[i] <= w0
                 while (lo < hi) {
@@ -377,20 +392,22 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                     if (winp[mid] <= w0) lo = mid; else hi = mid - 1;
                 }
                 lo = __builtin_amdgcn_readfirstlane(lo);
-                uint32_t wi = w0 - winp[lo];
-                uint32_t lo_n = ((lo + 1 < n_items) ? winp[lo + 1] : total_w) - winp[lo];
+                uint32_t wi = __builtin_amdgcn_readfirstlane(w0 - winp[lo]);
+                uint32_t lo_n = __builtin_amdgcn_readfirstlane(((lo + 1 < n_items) ? winp[lo + 1] : total_w) - winp[lo]);
                 uint64_t vs[WIN_BATCH];
                 uint64_t ms[WIN_BATCH];
                 uint32_t ps[WIN_BATCH];
                 uint4 its[WIN_BATCH];
                 uint32_t qs[WIN_BATCH];
+                uint32_t wis[WIN_BATCH];
+                // stage 1: which item and window each batch slot is (wave-uniform)
 #pragma unroll
                 for (int g = 0; g < WIN_BATCH; ++g) {
                     if (g > 0) {
                         if (wi + 1u >= lo_n && lo + 1 < n_items) {
                             ++lo;
                             wi = 0;
-                            lo_n = ((lo + 1 < n_items) ? winp[lo + 1] : total_w) - winp[lo];
+                            lo_n = __builtin_amdgcn_readfirstlane(((lo + 1 < n_items) ? winp[lo + 1] : total_w) - winp[lo]);
                         } else {
                             ++wi;
                         }
@@ -401,26 +418,39 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                     it.z = __builtin_amdgcn_readfirstlane(it.z);
                     it.w = __builtin_amdgcn_readfirstlane(it.w);
                     its[g] = it;
+                    wis[g] = wi;
+                }
+                // stage 2: descriptors of the bitmaps involved (scalar loads)
+                const uint64_t* wpt[WIN_BATCH];
+                const uint64_t* mpt[WIN_BATCH];
+                const uint32_t* ppt[WIN_BATCH];
+#pragma unroll
+                for (int g = 0; g < WIN_BATCH; ++g) {
+                    const EWT_GLOBAL BitmapDev* B = gp(table) + its[g].x;
+                    wpt[g] = B->words;
+                    mpt[g] = B->mmask;
+                    ppt[g] = B->mpos;
+                }
+                // stage 3: all data loads of the batch
+#pragma unroll
+                for (int g = 0; g < WIN_BATCH; ++g) {
+                    const uint4 it = its[g];
                     vs[g] = 0;
                     ms[g] = 0;
                     ps[g] = 0;
                     qs[g] = 0;
                     if (w0 + (uint32_t)g < total_w) {
-                        const BitmapDev* B = &table[it.x];
                         if (it.w & 0x80000000u) {
-                            const uint32_t qv = it.y + wi * 64u + (uint32_t)lane;
+                            const uint32_t qv = it.y + wis[g] * 64u + (uint32_t)lane;
                             qs[g] = qv;
-                            if (qv < it.z) vs[g] = __builtin_nontemporal_load(B->words + qv);
+                            if (qv < it.z) vs[g] = __builtin_nontemporal_load(gp(wpt[g]) + qv);
                         } else {
-                            const uint32_t c = (it.y >> 6) + wi;
+                            const uint32_t c = (it.y >> 6) + wis[g];
                             const uint32_t qv = c * 64u + (uint32_t)lane;
                             qs[g] = qv;
-                            vs[g] = __builtin_nontemporal_load(B->words + qv);
-                            const uint64_t mk = B->mmask[c];
-                            // readfirstlane returns int: widen through uint32_t, never sign-extend
-                            ms[g] = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(mk >> 32)) << 32) |
-                                    (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)mk);
-                            ps[g] = __builtin_amdgcn_readfirstlane(B->mpos[c]);
+                            vs[g] = __builtin_nontemporal_load(gp(wpt[g]) + qv);
+                            ms[g] = gp(mpt[g])[c];
+                            ps[g] = gp(ppt[g])[c];
                         }
                     }
                 }
@@ -480,7 +510,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                 for (; d + 16u <= n_dense; d += 16u) {
                     uint64_t x[16];
 #pragma unroll
-                    for (int j = 0; j < 16; ++j) x[j] = __builtin_nontemporal_load(dense[d + j] + tid);
+                    for (int j = 0; j < 16; ++j) x[j] = __builtin_nontemporal_load(gp(dense[d + j]) + tid);
                     uint64_t twosA, twosB, foursA, foursB, eightsA, eightsB, sixteens;
                     EWT_CSA(twosA, R[0], R[0], x[0], x[1]);
                     EWT_CSA(twosB, R[0], R[0], x[2], x[3]);
@@ -502,7 +532,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                     for (int p = 4; p < MAXP; ++p) { uint64_t tt = R[p] & cy; R[p] ^= cy; cy = tt; }
                 }
                 for (; d < n_dense; ++d) {
-                    uint64_t cy = __builtin_nontemporal_load(dense[d] + tid);
+                    uint64_t cy = __builtin_nontemporal_load(gp(dense[d]) + tid);
 #pragma unroll
                     for (int p = 0; p < MAXP; ++p) { uint64_t tt = R[p] & cy; R[p] ^= cy; cy = tt; }
                 }
@@ -584,7 +614,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             A.lh_pos = 0; A.lh_out = 0;
         }
         A.bits = bits;
-        TileState* st = q.state;
+        EWT_GLOBAL TileState* st = gp(q.state);
         Agg X;
         X.n = 0; X.lh_pos = 0; X.lh_out = 0; X.bits = 3u << 2;
         Agg I = A;
@@ -607,7 +637,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     const uint32_t c0 = clsA[0];
     const uint32_t merge = (t > 0 && c0 != 2u && ((Xbits >> 2) & 3u) == c0) ? 1u : 0u;
     const uint64_t cap = q.cap;
-    uint64_t* out = q.out;
+    EWT_GLOBAL uint64_t* out = gp(q.out);
     auto out_of = [&](uint32_t i, uint32_t local_ex) -> uint32_t { return Xn + local_ex - (i > 0 ? merge : 0u); };
 
     if (act) {
@@ -649,7 +679,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         uint32_t K = total - lout - 1u;
         uint32_t L = (U - lpos) - K;
         if (lout < cap) out[lout] = lf | ((uint64_t)L << 1) | ((uint64_t)K << 33);
-        *q.out_n = total;
+        *gp(q.out_n) = total;
     }
     __syncthreads();
     EWT_PHASE(7);
@@ -669,7 +699,7 @@ __global__ __launch_bounds__(BLOCK) void thr_query_kernel(QueryDev q, const Bitm
         s_t = t;
     }
     __syncthreads();
-    process_tile(q, table, s_t, epoch, smem, err);
+    process_tile(q, table, s_t, epoch, smem, err, s_t);
 }
 
 // Many queries in one persistent launch: workgroups take (query, tile) items
@@ -701,7 +731,7 @@ __global__ __launch_bounds__(BLOCK) void thr_batch_kernel(const QueryDev* __rest
         const uint32_t it = s_item, qi = s_q;
         if (it >= total) break;
         QueryDev q = qs[qi];
-        process_tile(q, table, it - qtile[qi], epoch, smem, err);
+        process_tile(q, table, it - qtile[qi], epoch, smem, err, it);
     }
 }
 
