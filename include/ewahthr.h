@@ -182,6 +182,65 @@ void ewah_batch_free(ewah_batch* b);
  */
 ewah_status ewah_device_errors(uint32_t* flags);
 
+/* ------------------------------------------------------ learned selection */
+
+/*
+ * Per-query features (16 floats, row-major [nq][16]) computed on the device
+ * from the registration catalog of the query's inputs: log2 N, log2 T, T/N,
+ * log2(N - T + 1), mean / max / min / standard deviation of log2 density,
+ * log2 of total and largest RunCount, log2 of total and largest compressed
+ * size, dirty-word fraction, log2 r, (sum of densities) / T, and a constant 1.
+ * These are the statistics the paper's hybrid assumes a database keeps
+ * (compressed sizes, cardinalities, Section 8.1).  idx / offs / T are host
+ * arrays: query q has inputs pool[idx[offs[q] .. offs[q+1])] and threshold
+ * T[q].  feat_dev is device memory.  Asynchronous on hip_stream.
+ */
+ewah_status ewah_query_features(const ewah_bitmap* const* pool, uint32_t pool_n, const uint32_t* idx,
+                                const uint32_t* offs, const uint32_t* T, uint32_t nq, float* feat_dev,
+                                void* hip_stream);
+
+/* Features of the queries of a planned batch (same definition). */
+ewah_status ewah_batch_features(ewah_batch* b, float* feat_dev, void* hip_stream);
+
+/*
+ * Picks, for every query of the batch, the variant with the smallest
+ * predicted cost: pred_dev is device memory [nq][n_arms] (e.g. the MLP's
+ * predicted log-times), arm_codes[n_arms] (host) the variant codes.  The
+ * choice is written into the batch's device query records (no host round
+ * trip); a following ewah_batch_run uses it.  Asynchronous on hip_stream.
+ */
+ewah_status ewah_batch_select(ewah_batch* b, const float* pred_dev, uint32_t n_arms, const uint32_t* arm_codes,
+                              void* hip_stream);
+
+/* Copies the variant codes currently stored in the batch's device query records to host (synchronous). */
+ewah_status ewah_batch_get_variants(ewah_batch* b, uint32_t* variants_host);
+
+/*
+ * FP32 multilayer perceptron 16 -> 64 -> 64 -> n_out (ReLU), the cost model
+ * of the selector.  Parameters live in device memory; layout (floats):
+ * W1[16][64], b1[64], W2[64][64], b2[64], W3[64][n_out], b3[n_out].
+ * Initialisation: He-uniform from a counter-based SplitMix64 stream of seed.
+ */
+typedef struct ewah_mlp ewah_mlp;
+ewah_status ewah_mlp_create(uint32_t n_out, uint64_t seed, ewah_mlp** out);
+void ewah_mlp_free(ewah_mlp* m);
+uint64_t ewah_mlp_num_params(uint32_t n_out);
+ewah_status ewah_mlp_get_params(const ewah_mlp* m, float* host, uint64_t n);
+ewah_status ewah_mlp_set_params(ewah_mlp* m, const float* host, uint64_t n);   /* also resets Adam state */
+/* y_dev[batch][n_out] = network(x_dev[batch][16]) (device memory, asynchronous) */
+ewah_status ewah_mlp_forward(ewah_mlp* m, const float* x_dev, uint32_t batch, float* y_dev, void* hip_stream);
+/*
+ * Gradient of the loss mean over (sample, output) of (y - t)^2 with respect
+ * to every parameter, into grad_dev (device, num_params floats, overwritten),
+ * loss into *loss_dev (device).  Asynchronous.
+ */
+ewah_status ewah_mlp_grad(ewah_mlp* m, const float* x_dev, const float* t_dev, uint32_t batch, float* grad_dev,
+                          float* loss_dev, void* hip_stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the same loss; loss before the step into *loss_dev. */
+ewah_status ewah_mlp_train_step(ewah_mlp* m, const float* x_dev, const float* t_dev, uint32_t batch, float lr,
+                                float* loss_dev, void* hip_stream);
+const char* ewah_mlp_last_error(void);
+
 /* Number of compute units of the device (0 before ewah_init). */
 uint32_t ewah_num_cus(void);
 

@@ -17,12 +17,12 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libewahthr.so")
 GENLIB = os.path.join(HERE, "datagen", "libewahgen.so")
 
-HIP_SOURCES = ["thr_tile.hip", "thr_api.cpp", "mlp.hip"]
+HIP_SOURCES = ["thr_tile.hip", "thr_api.cpp", "select.hip", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HIP_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-x", "hip",
-    # packed fp32 instructions stay off (known-bad forms on this target)
+    # packed fp32 instructions stay off: some of their forms have given wrong results on this target
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]

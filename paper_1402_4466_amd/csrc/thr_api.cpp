@@ -65,8 +65,10 @@ struct Lib {
     uint32_t n_cu = 0;
     size_t max_smem = 0;
     std::vector<BitmapDev> table;  // host mirror
+    std::vector<float4> stats;     // per slot: (n_words, n_literals, popcount, run_count) for features
     std::vector<uint32_t> free_slots;
     BitmapDev* d_table = nullptr;
+    float4* d_stats = nullptr;
     size_t d_table_cap = 0;
     uint32_t* d_err = nullptr;
     std::map<hipStream_t, Ctx> ctx;
@@ -171,13 +173,19 @@ ewah_status table_sync() {
         while (cap < g.table.size()) cap *= 2;
         HIPCHK(hipDeviceSynchronize());
         BitmapDev* nd = nullptr;
+        float4* ns = nullptr;
         HIPCHK(hipMalloc(&nd, cap * sizeof(BitmapDev)));
+        HIPCHK(hipMalloc(&ns, cap * sizeof(float4)));
         if (g.d_table) HIPCHK(hipFree(g.d_table));
+        if (g.d_stats) HIPCHK(hipFree(g.d_stats));
         g.d_table = nd;
+        g.d_stats = ns;
         g.d_table_cap = cap;
     }
-    if (!g.table.empty())
+    if (!g.table.empty()) {
         HIPCHK(hipMemcpy(g.d_table, g.table.data(), g.table.size() * sizeof(BitmapDev), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(g.d_stats, g.stats.data(), g.stats.size() * sizeof(float4), hipMemcpyHostToDevice));
+    }
     return EWAH_OK;
 }
 
@@ -188,6 +196,7 @@ uint32_t alloc_slot() {
         return s;
     }
     g.table.push_back(BitmapDev{});
+    g.stats.push_back(make_float4(0, 0, 0, 0));
     return (uint32_t)(g.table.size() - 1);
 }
 
@@ -332,6 +341,8 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
         arena->refs++;
         b->slot = alloc_slot();
         g.table[b->slot] = b->dev;
+        g.stats[b->slot] = make_float4((float)b->stats.n_words, (float)b->stats.n_literals, (float)b->stats.popcount,
+                                       (float)b->stats.run_count);
         out[i] = b;
     }
     return table_sync();
@@ -344,6 +355,7 @@ ewah_status ewah_register(const ewah_view* v, int on_device, ewah_bitmap** out) 
 void ewah_release(ewah_bitmap* b) {
     if (!b) return;
     g.table[b->slot] = BitmapDev{};
+    g.stats[b->slot] = make_float4(0, 0, 0, 0);
     g.free_slots.push_back(b->slot);
     if (--b->arena->refs == 0) {
         (void)hipDeviceSynchronize();
@@ -442,6 +454,9 @@ struct ewah_batch {
     uint32_t* d_ids = nullptr;
     TileState* d_state = nullptr;
     uint32_t* d_work = nullptr;    // work counter, epoch
+    uint32_t* d_codes = nullptr;   // variant codes for ewah_batch_select
+    std::vector<uint32_t> h_codes; // their host copy (upload only on change)
+    uint64_t n_bits = 0;
     uint32_t nq = 0;
     uint32_t grid = 0;
     size_t smem = 0;
@@ -520,6 +535,8 @@ ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, con
     HIPCHK(hipMemcpy(b->d_qtile, qtile.data(), (nq + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMalloc(&b->d_work, 256));
     HIPCHK(hipMemset(b->d_work, 0, 256));
+    HIPCHK(hipMalloc(&b->d_codes, 64 * 4));
+    b->n_bits = n_bits;
     b->h_qs.resize(nq);
     for (uint32_t i = 0; i < nq; ++i) {
         QueryDev& d = b->h_qs[i];
@@ -584,7 +601,81 @@ void ewah_batch_free(ewah_batch* b) {
     (void)hipFree(b->d_ids);
     (void)hipFree(b->d_state);
     (void)hipFree(b->d_work);
+    (void)hipFree(b->d_codes);
     delete b;
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------- learned selection
+
+extern "C" {
+
+ewah_status ewah_query_features(const ewah_bitmap* const* pool, uint32_t pool_n, const uint32_t* idx,
+                                const uint32_t* offs, const uint32_t* T, uint32_t nq, float* feat_dev,
+                                void* hip_stream) {
+    ewah_status st = ensure_ready();
+    if (st) return st;
+    if (nq == 0) return EWAH_OK;
+    if (!pool || !idx || !offs || !T || !feat_dev || pool_n == 0) return fail(EWAH_EINVAL, "null argument");
+    const uint64_t n_bits = pool[0]->stats.n_bits;
+    const uint32_t total = offs[nq];
+    std::vector<uint32_t> slots(total);
+    for (uint32_t i = 0; i < total; ++i) {
+        if (idx[i] >= pool_n || !pool[idx[i]]) return fail(EWAH_EINVAL, "pool index out of range");
+        slots[i] = pool[idx[i]]->slot;
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    uint32_t* d_slots = nullptr;
+    QueryDev* d_q = nullptr;
+    HIPCHK(hipMalloc(&d_slots, std::max<size_t>(total, 1) * 4));
+    HIPCHK(hipMalloc(&d_q, (size_t)nq * sizeof(QueryDev)));
+    std::vector<QueryDev> hq(nq);
+    for (uint32_t q = 0; q < nq; ++q) {
+        QueryDev d{};
+        d.ids = d_slots + offs[q];
+        d.N = offs[q + 1] - offs[q];
+        d.T = T[q];
+        hq[q] = d;
+    }
+    HIPCHK(hipMemcpy(d_slots, slots.data(), (size_t)total * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d_q, hq.data(), (size_t)nq * sizeof(QueryDev), hipMemcpyHostToDevice));
+    HIPCHK(launch_features(d_q, nq, g.d_stats, (float)n_bits, feat_dev, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipFree(d_slots));
+    HIPCHK(hipFree(d_q));
+    return EWAH_OK;
+}
+
+ewah_status ewah_batch_features(ewah_batch* b, float* feat_dev, void* hip_stream) {
+    if (!b || !feat_dev) return fail(EWAH_EINVAL, "null argument");
+    HIPCHK(launch_features(b->d_qs, b->nq, g.d_stats, (float)b->n_bits, feat_dev, (hipStream_t)hip_stream));
+    return EWAH_OK;
+}
+
+ewah_status ewah_batch_select(ewah_batch* b, const float* pred_dev, uint32_t n_arms, const uint32_t* arm_codes,
+                              void* hip_stream) {
+    if (!b || !pred_dev || !arm_codes || n_arms == 0 || n_arms > 64) return fail(EWAH_EINVAL, "bad arguments");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (b->h_codes.size() != n_arms || std::memcmp(b->h_codes.data(), arm_codes, n_arms * 4) != 0) {
+        HIPCHK(hipStreamSynchronize(s));   // d_codes may still be read by an earlier selection
+        HIPCHK(hipMemcpy(b->d_codes, arm_codes, n_arms * 4, hipMemcpyHostToDevice));
+        b->h_codes.assign(arm_codes, arm_codes + n_arms);
+    }
+    HIPCHK(launch_select(pred_dev, b->nq, n_arms, b->d_codes, b->d_qs, s));
+    return EWAH_OK;
+}
+
+ewah_status ewah_batch_get_variants(ewah_batch* b, uint32_t* variants_host) {
+    if (!b || !variants_host) return fail(EWAH_EINVAL, "null argument");
+    HIPCHK(hipDeviceSynchronize());
+    std::vector<QueryDev> hq(b->nq);
+    HIPCHK(hipMemcpy(hq.data(), b->d_qs, b->nq * sizeof(QueryDev), hipMemcpyDeviceToHost));
+    for (uint32_t i = 0; i < b->nq; ++i) {
+        variants_host[i] = hq[i].variant;
+        b->h_qs[i].variant = hq[i].variant;
+    }
+    return EWAH_OK;
 }
 
 }  // extern "C"

@@ -129,5 +129,8 @@ hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, uint32_t nq, 
 hipError_t launch_bump(uint32_t* epoch, hipStream_t s);
 hipError_t launch_zero_len(uint64_t* out_n, hipStream_t s);
 hipError_t set_smem_limits(size_t max_bytes);
+hipError_t launch_features(const QueryDev* qs, uint32_t nq, const float4* stats, float r, float* feat, hipStream_t s);
+hipError_t launch_select(const float* pred, uint32_t nq, uint32_t n_arms, const uint32_t* codes, QueryDev* qs,
+                         hipStream_t s);
 
 }  // namespace ewt

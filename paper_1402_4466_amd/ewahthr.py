@@ -77,12 +77,28 @@ _batch_set_grid = _sig("ewah_batch_set_grid", _i32, [_vp, _u32])
 _batch_free = _sig("ewah_batch_free", None, [_vp])
 _device_errors = _sig("ewah_device_errors", _i32, [ctypes.POINTER(_u32)])
 _num_cus = _sig("ewah_num_cus", _u32, [])
+_query_features = _sig("ewah_query_features", _i32, [ctypes.POINTER(_vp), _u32, _vp, _vp, _vp, _u32, _vp, _vp])
+_batch_features = _sig("ewah_batch_features", _i32, [_vp, _vp, _vp])
+_batch_select = _sig("ewah_batch_select", _i32, [_vp, _vp, _u32, _vp, _vp])
+_batch_get_variants = _sig("ewah_batch_get_variants", _i32, [_vp, _vp])
+_mlp_create = _sig("ewah_mlp_create", _i32, [_u32, _u64, ctypes.POINTER(_vp)])
+_mlp_free = _sig("ewah_mlp_free", None, [_vp])
+_mlp_num_params = _sig("ewah_mlp_num_params", _u64, [_u32])
+_mlp_get_params = _sig("ewah_mlp_get_params", _i32, [_vp, _vp, _u64])
+_mlp_set_params = _sig("ewah_mlp_set_params", _i32, [_vp, _vp, _u64])
+_mlp_forward = _sig("ewah_mlp_forward", _i32, [_vp, _vp, _u32, _vp, _vp])
+_mlp_grad = _sig("ewah_mlp_grad", _i32, [_vp, _vp, _vp, _u32, _vp, _vp, _vp])
+_mlp_train_step = _sig("ewah_mlp_train_step", _i32, [_vp, _vp, _vp, _u32, ctypes.c_float, _vp, _vp])
+_mlp_last_error = _sig("ewah_mlp_last_error", ctypes.c_char_p, [])
 
 EXPORTED = ["ewah_init", "ewah_last_error", "ewah_register", "ewah_register_many", "ewah_release",
             "ewah_get_stats", "ewah_device_words", "ewah_output_bound", "ewah_threshold", "ewah_threshold_v",
             "ewah_variant_code", "ewah_default_variant", "ewah_batch_plan", "ewah_batch_run",
             "ewah_batch_set_variants", "ewah_batch_set_grid", "ewah_batch_free", "ewah_device_errors",
-            "ewah_num_cus"]
+            "ewah_num_cus", "ewah_query_features", "ewah_batch_features", "ewah_batch_select",
+            "ewah_batch_get_variants", "ewah_mlp_create", "ewah_mlp_free", "ewah_mlp_num_params",
+            "ewah_mlp_get_params", "ewah_mlp_set_params", "ewah_mlp_forward", "ewah_mlp_grad",
+            "ewah_mlp_train_step", "ewah_mlp_last_error"]
 
 
 class EwahError(RuntimeError):
@@ -223,9 +239,87 @@ class Batch:
     def set_grid(self, grid: int):
         _check(_batch_set_grid(self._h, grid), "batch_set_grid")
 
+    def features(self, feat_ptr: int, stream=None):
+        _check(_batch_features(self._h, feat_ptr, _stream_ptr(stream)), "batch_features")
+
+    def select(self, pred_ptr: int, arm_codes, stream=None):
+        a = np.ascontiguousarray(np.asarray(arm_codes, dtype=np.uint32))
+        self._codes = a
+        _check(_batch_select(self._h, pred_ptr, len(a), a.ctypes.data, _stream_ptr(stream)), "batch_select")
+
+    def set_arm_codes(self, arm_codes):
+        self._codes = np.ascontiguousarray(np.asarray(arm_codes, dtype=np.uint32))
+
+    def select_async(self, pred_ptr: int, stream=None):
+        """Device argmin over pred [nq][K] with the arm codes set by set_arm_codes."""
+        a = self._codes
+        _check(_batch_select(self._h, pred_ptr, len(a), a.ctypes.data, _stream_ptr(stream)), "batch_select")
+
+    def get_variants(self) -> np.ndarray:
+        out = np.zeros(self.nq, dtype=np.uint32)
+        _check(_batch_get_variants(self._h, out.ctypes.data), "batch_get_variants")
+        return out
+
     def free(self):
         if self._h:
             _batch_free(self._h)
+            self._h = None
+
+
+def query_features(pool, queries, feat_ptr: int, stream=None):
+    """Device features [nq][16] of queries (idx, T) over registered pool bitmaps."""
+    pool_arr = (_vp * len(pool))(*[b.handle for b in pool])
+    offs = np.zeros(len(queries) + 1, dtype=np.uint32)
+    for i, (idx, _) in enumerate(queries):
+        offs[i + 1] = offs[i] + len(idx)
+    idx = np.ascontiguousarray(np.concatenate([np.asarray(q[0], dtype=np.uint32) for q in queries])
+                               if queries else np.zeros(0, dtype=np.uint32))
+    T = np.ascontiguousarray(np.array([q[1] for q in queries], dtype=np.uint32))
+    _check(_query_features(pool_arr, len(pool), idx.ctypes.data, offs.ctypes.data, T.ctypes.data, len(queries),
+                           feat_ptr, _stream_ptr(stream)), "query_features")
+
+
+class MLPError(RuntimeError):
+    pass
+
+
+def _mcheck(code, where):
+    if code != OK:
+        raise MLPError(f"{where}: status {code}: {_mlp_last_error().decode(errors='replace')}")
+
+
+class MLP:
+    """Handle of the library's FP32 16 -> 64 -> 64 -> n_out MLP (device-resident parameters)."""
+
+    def __init__(self, n_out: int, seed: int = 1):
+        h = _vp()
+        _mcheck(_mlp_create(n_out, seed, ctypes.byref(h)), "mlp_create")
+        self._h = h
+        self.n_out = n_out
+        self.n_params = int(_mlp_num_params(n_out))
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.n_params, dtype=np.float32)
+        _mcheck(_mlp_get_params(self._h, a.ctypes.data, self.n_params), "mlp_get_params")
+        return a
+
+    def set_params(self, p) -> None:
+        a = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        assert a.size == self.n_params
+        _mcheck(_mlp_set_params(self._h, a.ctypes.data, self.n_params), "mlp_set_params")
+
+    def forward(self, x_ptr: int, batch: int, y_ptr: int, stream=None):
+        _mcheck(_mlp_forward(self._h, x_ptr, batch, y_ptr, _stream_ptr(stream)), "mlp_forward")
+
+    def grad(self, x_ptr: int, t_ptr: int, batch: int, g_ptr: int, loss_ptr: int, stream=None):
+        _mcheck(_mlp_grad(self._h, x_ptr, t_ptr, batch, g_ptr, loss_ptr, _stream_ptr(stream)), "mlp_grad")
+
+    def train_step(self, x_ptr: int, t_ptr: int, batch: int, lr: float, loss_ptr: int, stream=None):
+        _mcheck(_mlp_train_step(self._h, x_ptr, t_ptr, batch, lr, loss_ptr, _stream_ptr(stream)), "mlp_train_step")
+
+    def free(self):
+        if self._h:
+            _mlp_free(self._h)
             self._h = None
 
 

@@ -1,17 +1,23 @@
 """Per-query kernel-variant selection.
 
-Features come from the per-bitmap catalog computed at registration (the kind
-of statistics the paper's hybrid assumes a database keeps: compressed size,
-cardinality, run counts -- Section 8.1).  Three selectors share one interface:
+Every variant ("arm") computes the same canonical result; they differ in how
+the tile routine spends its work (dense carry-save rows or sparse ripple adds
+for whole-tile dirty runs; how long a segment may be before it is split across
+a wavefront).  Three selectors share one interface:
 
-  RuleSelector     paper-style rules (RBMrg case analysis of Section 6.4 and the
-                   cost-model comparison of Section 8.2), with constants refit
-                   from timings on this GPU;
-  MLPSelector      FP32 MLP 16 -> 64 -> 64 -> K predicting log-time of each
-                   variant; trained and evaluated by the library's HIP kernels
-                   (machine-learned algorithm selection is the paper's stated
-                   future work, Section 9);
-  FixedSelector    one variant for every query.
+  MLPSelector   learned cost model: features computed on the device from the
+                registration catalog, FP32 MLP (HIP kernels) predicting the
+                log-time of every arm, per-query argmin written straight into
+                the batch's device query records;
+  RuleSelector  paper-style rules: a running-time model per arm of the form
+                c1 * EWAHSize + c2 * EWAHSize * ln N + c3 * N * tiles + c4 * T *
+                EWAHSize, fitted by least squares to measured times (the
+                fitting procedure of Section 8.1), choosing the smallest
+                estimate (hybrid H, Section 8.2);
+  FixedSelector one arm for every query.
+
+Exhaustive timing (the oracle selector H_opt of Section 8.2) is the judge of
+their regret; it lives in train_selector.py.
 """
 from __future__ import annotations
 
@@ -25,14 +31,14 @@ DEFAULT_MODEL = os.path.join(HERE, "selector_model.json")
 
 N_FEATURES = 16
 
-# Variant arms: (name, dense, walk, litwalk).  Results are identical for all arms.
+# Arms: (name, dense, walk, litwalk).  All compute identical outputs.
 ARMS = [
-    ("hybrid", True, 8, 8),
-    ("sparse", False, 8, 8),
-    ("dense_coop", True, 0, 0),
-    ("sparse_walk", False, 64, 64),
-    ("dense_walk", True, 32, 64),
-    ("sparse_coop", False, 0, 0),
+    ("hybrid_w8", True, 8, 8),
+    ("sparse_w8", False, 8, 8),
+    ("hybrid_coop", True, 0, 0),
+    ("sparse_walk64", False, 64, 64),
+    ("hybrid_walk32", True, 32, 64),
+    ("hybrid_walk128", True, 128, 255),
 ]
 
 
@@ -41,8 +47,9 @@ def arm_codes():
     return [E.variant_code(d, w, l) for (_, d, w, l) in ARMS]
 
 
-def features(queries, stats, n_bits: int) -> np.ndarray:
-    """[Q, 16] float32 features of each query (idx, T) from per-bitmap catalog stats."""
+def features_host(queries, stats, n_bits: int) -> np.ndarray:
+    """Reference definition of the 16 features in numpy (the device kernel computes
+    the same in FP32; used by tests and the rule set)."""
     nw = np.array([s["n_words"] for s in stats], dtype=np.float64)
     lit = np.array([s["n_literals"] for s in stats], dtype=np.float64)
     pop = np.array([s["popcount"] for s in stats], dtype=np.float64)
@@ -50,23 +57,33 @@ def features(queries, stats, n_bits: int) -> np.ndarray:
     r = float(max(n_bits, 1))
     dens = np.maximum(pop / r, 1e-9)
     ld = np.log2(dens)
-    out = np.zeros((len(queries), N_FEATURES), dtype=np.float32)
+    out = np.zeros((len(queries), N_FEATURES), dtype=np.float64)
     for i, q in enumerate(queries):
-        idx = np.asarray(q.idx if hasattr(q, "idx") else q[0], dtype=np.int64)
-        T = float(q.T if hasattr(q, "T") else q[1])
+        idx = np.asarray(q[0], dtype=np.int64)
+        T = float(q[1])
         N = float(len(idx))
         d = ld[idx]
         w = nw[idx]
         ru = runs[idx]
         out[i] = [
             np.log2(N), np.log2(max(T, 1.0)), T / N, np.log2(N - min(T, N) + 1.0),
-            d.mean(), d.max(), d.min(), d.std(),
+            d.mean(), d.max(), d.min(), np.sqrt(max((d * d).mean() - d.mean() ** 2, 0.0)),
             np.log2(ru.sum() + 1.0), np.log2(ru.max() + 1.0),
             np.log2(w.sum() + 1.0), np.log2(w.max() + 1.0),
             lit[idx].sum() / max(w.sum(), 1.0), np.log2(r),
             dens[idx].sum() / max(T, 1.0), 1.0,
         ]
     return out
+
+
+def rule_regressors(feat: np.ndarray) -> np.ndarray:
+    """Regressors of the paper-style running-time model, from the features."""
+    ewah = 2.0 ** feat[:, 10] - 1.0            # total compressed words (EWAHSize / 8)
+    N = 2.0 ** feat[:, 0]
+    T = 2.0 ** feat[:, 1]
+    tiles = np.maximum(2.0 ** feat[:, 13] / 65536.0, 1.0)
+    lit = feat[:, 12] * ewah
+    return np.stack([ewah, ewah * np.log(np.maximum(N, 1.0)), N * tiles, T * ewah, lit], axis=1)
 
 
 class FixedSelector:
@@ -76,36 +93,46 @@ class FixedSelector:
         self.variant = variant
         self.grid = grid
 
-    def choose(self, feats, queries):
-        return [self.variant] * len(queries), f"fixed:{self.variant:#x}"
+    def choose_host(self, feat):
+        return np.full(len(feat), self.variant, dtype=np.uint32)
+
+    def apply(self, batch, pool, queries, n_bits, stream=None):
+        batch.set_variants(np.full(len(queries), self.variant, dtype=np.uint32))
+        return f"fixed:{self.variant:#x}"
 
 
 class RuleSelector:
-    """Paper-style rule set.  Per query: if the inputs are dense enough that most
-    tiles are covered by whole-tile dirty runs, use the carry-save-adder arm; if
-    they are sparse (few words per tile per input), walk segments with single
-    lanes; otherwise the hybrid default.  Thresholds are refit by the tuner."""
     kind = "rules"
 
-    def __init__(self, dense_lit_frac: float = 0.6, walk_words_per_tile: float = 24.0, grid: int = 0):
-        self.dense_lit_frac = dense_lit_frac
-        self.walk_words_per_tile = walk_words_per_tile
+    def __init__(self, coef: np.ndarray, codes, grid: int = 0):
+        self.coef = np.asarray(coef, dtype=np.float64)     # [n_regressors, K]
+        self.codes = [int(c) for c in codes]
         self.grid = grid
 
-    def choose(self, feats, queries):
-        codes = arm_codes()
-        out = []
-        tiles = np.maximum(2.0 ** feats[:, 13] / 65536.0, 1.0)
-        for i in range(len(queries)):
-            lit_frac = feats[i, 12]
-            words_per_tile_per_input = 2.0 ** feats[i, 10] / tiles[i] / 2.0 ** feats[i, 0]
-            if lit_frac >= self.dense_lit_frac:
-                out.append(codes[0])
-            elif words_per_tile_per_input <= self.walk_words_per_tile:
-                out.append(codes[3])
-            else:
-                out.append(codes[0])
-        return out, "rules"
+    @staticmethod
+    def fit(feat: np.ndarray, times: np.ndarray) -> np.ndarray:
+        """Least squares through the origin per arm (Section 8.1): times [n, K] in microseconds."""
+        X = rule_regressors(feat)
+        coef = np.zeros((X.shape[1], times.shape[1]))
+        for k in range(times.shape[1]):
+            coef[:, k], *_ = np.linalg.lstsq(X, times[:, k], rcond=None)
+        return coef
+
+    def predict(self, feat):
+        return rule_regressors(feat) @ self.coef
+
+    def choose_arm(self, feat):
+        return np.argmin(self.predict(feat), axis=1)
+
+    def choose_host(self, feat):
+        return np.asarray([self.codes[j] for j in self.choose_arm(feat)], dtype=np.uint32)
+
+    def apply(self, batch, pool, queries, n_bits, stream=None):
+        import torch
+        feat = torch.zeros((len(queries), N_FEATURES), dtype=torch.float32, device="cuda")
+        batch.features(feat.data_ptr(), stream)
+        batch.set_variants(self.choose_host(feat.cpu().numpy().astype(np.float64)))
+        return "rules"
 
 
 class MLPSelector:
@@ -114,15 +141,42 @@ class MLPSelector:
     def __init__(self, model: dict):
         self.model = model
         self.grid = int(model.get("grid", 0))
+        self.codes = [int(c) for c in model["arm_codes"]]
+        self._pred = None
 
-    def predict(self, feats):
-        from . import mlp
-        return mlp.infer(self.model, feats)
+    def predictor(self):
+        if self._pred is None:
+            from .mlp import Predictor
+            self._pred = Predictor(self.model)
+        return self._pred
 
-    def choose(self, feats, queries):
-        codes = [int(c) for c in self.model["arm_codes"]]
-        pred = self.predict(feats)
-        return [codes[int(j)] for j in np.argmin(pred, axis=1)], "mlp"
+    def prepare(self, batch, nq: int):
+        """Device buffers for per-step selection on one batch."""
+        import torch
+        self._batch = batch
+        self._nq = nq
+        self._feat = torch.zeros((nq, N_FEATURES), dtype=torch.float32, device="cuda")
+        self._predbuf = torch.zeros((nq, len(self.codes)), dtype=torch.float32, device="cuda")
+        self.predictor()
+
+    def apply_device(self, stream=None):
+        """Features -> MLP -> argmin, all on the device and asynchronous; the choice lands in the
+        batch's query records, read by the next run of the batch."""
+        self._batch.features(self._feat.data_ptr(), stream)
+        self._pred.forward(self._feat.data_ptr(), self._nq, self._predbuf.data_ptr(), stream)
+        self._batch.select_async(self._predbuf.data_ptr(), stream)
+
+    def apply(self, batch, pool, queries, n_bits, stream=None):
+        self.prepare(batch, len(queries))
+        batch.set_arm_codes(self.codes)
+        self.apply_device(stream)
+        return "mlp"
+
+    def choose_device_arms(self, feat_ptr: int, n: int):
+        import torch
+        pred = torch.zeros((n, len(self.codes)), dtype=torch.float32, device="cuda")
+        self.predictor().forward(feat_ptr, n, pred.data_ptr())
+        return pred.argmin(dim=1).cpu().numpy()
 
 
 def load_selector(path: str | None = None):
@@ -134,7 +188,7 @@ def load_selector(path: str | None = None):
         if kind == "mlp":
             return MLPSelector(m)
         if kind == "rules":
-            return RuleSelector(m.get("dense_lit_frac", 0.6), m.get("walk_words_per_tile", 24.0), m.get("grid", 0))
+            return RuleSelector(np.asarray(m["coef"]), m["arm_codes"], m.get("grid", 0))
         if kind == "fixed":
             return FixedSelector(int(m.get("variant", 0)), int(m.get("grid", 0)))
     return FixedSelector(0, 0)
