@@ -147,6 +147,14 @@ def bench_c4(args, E, torch):
         f"output {out_words} words")
     # kernel-only time of the persistent launch (same stream, HIP events), for the roofline
     kms = events_time(lambda: batch.run(stream), stream, args.steps)
+    # the same batched launch with every query on the default variant (no selection)
+    learned_variants = batch.get_variants()
+    batch.set_variants(np.full(len(qs), E.default_variant(), dtype=np.uint32))
+    batch.run(stream)
+    dms = events_time(lambda: batch.run(stream), stream, args.steps)
+    batched_default = total_in / (dms / 1e3) / 1e9
+    batch.set_variants(learned_variants)
+    log(f"batched, default variant: {dms:.3f} ms/step, {batched_default:.1f} GB/s")
 
     plain = None
     if not args.no_plain:
@@ -183,6 +191,7 @@ def bench_c4(args, E, torch):
                    "path": "batched persistent graph launch", "selector": sel_kind, "grid": grid,
                    "input_bytes_per_step": total_in, "output_words_per_step": out_words},
         "plain_value": None if plain is None else round(plain, 2),
+        "batched_default_variant_value": round(batched_default, 2),
         "speedup_vs_plain": None if plain is None else round(value / plain, 3),
         "words_per_s": round(total_in / 8 / (ms / 1e3), 1),
         "roofline": roof,

@@ -52,7 +52,7 @@ def train(X: np.ndarray, Y: np.ndarray, epochs: int = 60, batch: int = 1024, lr:
     Xs = ((X - mu) / sd).astype(np.float32)
     Xs[:, -1] = 1.0
     ym = Y.mean()
-    Yc = (Y - ym).astype(np.float32)
+    Yc = (Y - ym).astype(np.float32)      # targets as given (the caller centres per query if it wants relative costs)
     net = E.MLP(k, seed)
     rng = np.random.default_rng(seed)
     dX = torch.empty((n, NI), dtype=torch.float32, device="cuda")
