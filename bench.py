@@ -82,13 +82,24 @@ def cpu_baseline(streams_of, n_bits, queries, seconds):
             "sample": f"first {done} of {len(queries)} queries ({words * 8 / 1e6:.1f} MB of input, {dt:.1f} s)"}
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    src = b"".join(open(os.path.join(ROOT, "paper_1402_4466_amd", "csrc", n), "rb").read()
+                   for n in ("thr_tile.hip", "thr_device.h"))
+    return hashlib.sha256(src).hexdigest()[:16]
+
+
 def load_traffic(path, kernel):
+    """Calibrated HBM bytes per launch from the committed counter runs, or None if
+    the kernel source changed since they were taken."""
     try:
         with open(path) as f:
-            t = json.load(f)
-        return t.get(kernel)
+            t = json.load(f).get(kernel)
     except Exception:
         return None
+    if not t or t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t["bytes_per_launch"]
 
 
 def bench_c4(args, E, torch):

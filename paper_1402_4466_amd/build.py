@@ -61,9 +61,20 @@ def build_hip() -> str:
     return LIB
 
 
+def build_tools() -> str:
+    """Measurement tool: streaming-read ceiling of the device (not part of the query path)."""
+    os.makedirs(os.path.join(HERE, "bin"), exist_ok=True)
+    exe = os.path.join(HERE, "bin", "stream_ceiling")
+    _run([HIPCC, "-O3", "--offload-arch=gfx950", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+          "-packed-fp32-ops", "-o", exe + ".tmp", os.path.join(CSRC, "stream_ceiling.hip")])
+    os.replace(exe + ".tmp", exe)
+    return exe
+
+
 def build_all() -> None:
     build_generator()
     build_hip()
+    build_tools()
 
 
 if __name__ == "__main__":
