@@ -84,9 +84,8 @@ ewah_status ensure_ready() {
 // ----------------------------------------------------------- index builder
 
 struct Built {
-    std::vector<uint2> loc;
-    std::vector<uint64_t> mmask;
-    std::vector<uint32_t> mpos;
+    std::vector<uint4> loc;    // per tile boundary: covering marker index, its run start, the marker word
+    std::vector<uint4> desc;   // per CHUNK words: marker mask (lo, hi), position of the chunk's first word
     ewah_stats st{};
 };
 
@@ -96,12 +95,11 @@ inline uint64_t popc64(uint64_t x) { return (uint64_t)__builtin_popcountll(x); }
 ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& b) {
     const uint64_t U = (n_bits + 63) / 64;
     if (U >= (1ull << 31)) return fail(EWAH_EINVAL, "n_bits too large (U must be < 2^31 words)");
-    if (nw >= (1ull << 32) - CHUNK) return fail(EWAH_EINVAL, "stream too long (n_words must be < 2^32 - 64)");
+    if (nw >= (1ull << 32) - 2 * CHUNK) return fail(EWAH_EINVAL, "stream too long (n_words must be < 2^32 - 128)");
     const uint64_t tiles = (U + TW - 1) / TW;
     const uint64_t nchunks = (nw + CHUNK - 1) / CHUNK;
-    b.loc.assign(tiles + 1, make_uint2(0, 0));
-    b.mmask.assign(nchunks, 0);
-    b.mpos.assign(nchunks, 0);
+    b.loc.assign(tiles + 1, make_uint4(0, 0, 0, 0));
+    b.desc.assign(nchunks, make_uint4(0, 0, 0, 0));
     const uint64_t tailmask = (n_bits % 64) ? ((1ull << (n_bits % 64)) - 1) : ~0ull;
     ewah_stats& st = b.st;
     st = ewah_stats{};
@@ -126,10 +124,13 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
         if (K > U - u - L) return fail(EWAH_EFORMAT, "marker at word " + std::to_string(p) + ": literal run past the end");
         st.n_markers++;
         const uint64_t c = p / CHUNK;
-        b.mmask[c] |= 1ull << (p - c * CHUNK);
-        if (p % CHUNK == 0) b.mpos[c] = (uint32_t)u;
+        const uint64_t bit = p - c * CHUNK;
+        if (bit < 32) b.desc[c].x |= 1u << bit;
+        else b.desc[c].y |= 1u << (bit - 32);
+        if (p % CHUNK == 0) b.desc[c].z = (uint32_t)u;
         if (L + K > 0) {
-            for (uint64_t t = (u + TW - 1) / TW; t * TW < u + L + K && t < tiles; ++t) b.loc[t] = make_uint2((uint32_t)p, (uint32_t)u);
+            const uint4 e = make_uint4((uint32_t)p, (uint32_t)u, (uint32_t)m, (uint32_t)(m >> 32));
+            for (uint64_t t = (u + TW - 1) / TW; t * TW < u + L + K && t < tiles; ++t) b.loc[t] = e;
         }
         // statistics over the fill run
         if (L) {
@@ -147,7 +148,7 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
         }
         for (uint64_t i = 0; i < K; ++i) {
             const uint64_t q = p + 1 + i, pos = u + L + i;
-            if (q % CHUNK == 0) b.mpos[q / CHUNK] = (uint32_t)pos;
+            if (q % CHUNK == 0) b.desc[q / CHUNK].z = (uint32_t)pos;
             uint64_t v = w[q];
             const uint64_t nbits = (pos == U - 1) ? (n_bits - (U - 1) * 64) : 64;
             if (pos == U - 1) v &= tailmask;
@@ -159,8 +160,8 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
         u += L + K;
     }
     if (u != U) return fail(EWAH_EFORMAT, "stream covers " + std::to_string(u) + " words, expected " + std::to_string(U));
-    if (tiles) b.loc[tiles] = make_uint2((uint32_t)nw, (uint32_t)U);
-    st.index_bytes = b.loc.size() * sizeof(uint2) + b.mmask.size() * 12;
+    if (tiles) b.loc[tiles] = make_uint4((uint32_t)nw, (uint32_t)U, 0, 0);
+    st.index_bytes = b.loc.size() * sizeof(uint4) + b.desc.size() * sizeof(uint4);
     return EWAH_OK;
 }
 
@@ -300,39 +301,54 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
         st = build_index(w, v[i].n_words, v[i].n_bits, built[i]);
         if (st) return fail(st, "bitmap " + std::to_string(i) + ": " + g_err);
     }
-    // one device arena: [words padded to CHUNK | marker masks | chunk positions | loc] per bitmap
-    std::vector<size_t> off(count + 1, 0);
+    // one device arena per call; per bitmap [words padded to CHUNK, plus CHUNK zero words |
+    // skip index | locator], each part 256-byte aligned.  The image is assembled on the host
+    // and uploaded in pieces of at most kStage bytes.
+    constexpr size_t kStage = 256ull << 20;
+    struct Layout { size_t words, desc, loc, end; };
+    std::vector<Layout> lay(count);
+    size_t total = 0;
     for (uint32_t i = 0; i < count; ++i) {
-        size_t nch = std::max<size_t>(built[i].mmask.size(), 1);
-        size_t sz = align256(nch * CHUNK * 8) + align256(nch * 8) + align256(nch * 4) + align256(built[i].loc.size() * 8);
-        off[i + 1] = off[i] + sz;
+        const size_t nch = std::max<size_t>(built[i].desc.size(), 1);
+        Layout& l = lay[i];
+        l.words = total;
+        l.desc = l.words + align256((nch * CHUNK + CHUNK) * 8);
+        l.loc = l.desc + align256(nch * 16);
+        l.end = l.loc + align256(built[i].loc.size() * 16);
+        total = l.end;
     }
     Arena* arena = new Arena();
-    if (hipMalloc(&arena->d, off[count]) != hipSuccess) {
+    if (hipMalloc(&arena->d, total) != hipSuccess) {
         delete arena;
-        return fail(EWAH_ENOMEM, "device allocation of " + std::to_string(off[count]) + " bytes failed");
+        return fail(EWAH_ENOMEM, "device allocation of " + std::to_string(total) + " bytes failed");
     }
-    // zero the whole arena so chunk padding reads zeros
-    HIPCHK(hipMemset(arena->d, 0, off[count]));
-    for (uint32_t i = 0; i < count; ++i) {
-        char* base = (char*)arena->d + off[i];
-        size_t nch = std::max<size_t>(built[i].mmask.size(), 1);
-        uint64_t* dw = (uint64_t*)base;
-        uint64_t* dmask = (uint64_t*)(base + align256(nch * CHUNK * 8));
-        uint32_t* dpos = (uint32_t*)(base + align256(nch * CHUNK * 8) + align256(nch * 8));
-        uint2* dloc = (uint2*)(base + align256(nch * CHUNK * 8) + align256(nch * 8) + align256(nch * 4));
-        const uint64_t* src = on_device ? host[i].data() : v[i].words;
-        if (v[i].n_words) HIPCHK(hipMemcpy(dw, src, v[i].n_words * 8, hipMemcpyHostToDevice));
-        if (!built[i].mmask.empty()) {
-            HIPCHK(hipMemcpy(dmask, built[i].mmask.data(), built[i].mmask.size() * 8, hipMemcpyHostToDevice));
-            HIPCHK(hipMemcpy(dpos, built[i].mpos.data(), built[i].mpos.size() * 4, hipMemcpyHostToDevice));
+    if (((uintptr_t)arena->d + total) >> 48) {   // window addresses carry flags in their top 16 bits
+        (void)hipFree(arena->d);
+        delete arena;
+        return fail(EWAH_EDEVICE, "device address above 2^48");
+    }
+    std::vector<char> stage;
+    for (uint32_t i0 = 0; i0 < count;) {
+        uint32_t i1 = i0 + 1;
+        while (i1 < count && lay[i1].end - lay[i0].words <= kStage) ++i1;
+        const size_t base = lay[i0].words, len = lay[i1 - 1].end - base;
+        stage.assign(len, 0);
+        for (uint32_t i = i0; i < i1; ++i) {
+            const uint64_t* src = on_device ? host[i].data() : v[i].words;
+            if (v[i].n_words) std::memcpy(stage.data() + (lay[i].words - base), src, v[i].n_words * 8);
+            if (!built[i].desc.empty())
+                std::memcpy(stage.data() + (lay[i].desc - base), built[i].desc.data(), built[i].desc.size() * 16);
+            std::memcpy(stage.data() + (lay[i].loc - base), built[i].loc.data(), built[i].loc.size() * 16);
         }
-        HIPCHK(hipMemcpy(dloc, built[i].loc.data(), built[i].loc.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy((char*)arena->d + base, stage.data(), len, hipMemcpyHostToDevice));
+        i0 = i1;
+    }
+    for (uint32_t i = 0; i < count; ++i) {
+        char* base = (char*)arena->d;
         ewah_bitmap* b = new ewah_bitmap();
-        b->dev.words = dw;
-        b->dev.loc = dloc;
-        b->dev.mmask = dmask;
-        b->dev.mpos = dpos;
+        b->dev.words = (const uint64_t*)(base + lay[i].words);
+        b->dev.loc = (const uint4*)(base + lay[i].loc);
+        b->dev.desc = (const uint4*)(base + lay[i].desc);
         b->dev.pad = 0;
         b->dev.n_words = (uint32_t)v[i].n_words;
         b->dev.U = (uint32_t)((v[i].n_bits + 63) / 64);

@@ -4,21 +4,23 @@
 // One workgroup computes the output of one tile of TW consecutive uncompressed
 // word positions (TW * 64 rows) over all N inputs:
 //   1. segment location: per input, the per-tile locator built at registration
-//      gives the marker whose run covers the tile start; its header and the
-//      header of the marker covering the next tile start bound the input's
-//      compressed words that touch the tile (EWAH markers carry both the fill
-//      length and the dirty-word count, so dirty runs are skipped without
-//      reading them -- Section 3.1);
+//      holds the marker whose run covers the tile start together with that
+//      marker word, so the covering marker and the one covering the next tile
+//      start bound the input's compressed words that touch the tile without
+//      reading the stream (EWAH markers carry both the fill length and the
+//      dirty-word count, so dirty runs are skipped without reading them --
+//      Section 3.1);
 //   2. classify / prune: inputs whose one-fill covers the whole tile and inputs
 //      that can hold a one in the tile are counted; the three cases of RBMrg on
 //      EWAH (Section 6.4) at tile granularity: >= T full one-fills -> all ones,
 //      fewer than T non-empty inputs -> all zeros, else count;
-//   3. decode: short segments are walked by one lane; long ones are split into
-//      64-word windows aligned to the compressed stream, each decoded by one
-//      wavefront: the skip index gives the window's marker mask (built at
-//      registration by following the marker chain next = p + 1 + K) and the
-//      position of its first word, and a wavefront prefix scan of the words'
-//      spans (L for a marker, 1 for a dirty word) gives every word's
+//   3. decode: short segments are walked by one lane (eight words per read);
+//      long ones are cut into 64-word windows aligned to the compressed
+//      stream, listed in LDS and shared out among the wavefronts, each window
+//      decoded by one wavefront: the skip index gives the window's marker mask
+//      (built at registration by following the marker chain next = p + 1 + K)
+//      and the position of its first word, and a wavefront prefix scan of the
+//      words' spans (L for a marker, 1 for a dirty word) gives every word's
 //      uncompressed position;
 //   4. count: dirty words are added into a bit-sliced per-row counter in LDS
 //      (planes A_1..A_P, least significant first, as in the bit-sliced index of
@@ -49,10 +51,12 @@ constexpr uint32_t MAXN = (1u << MAXP) - 1;
 
 // Registered bitmap as seen by the kernels (48 bytes).
 struct BitmapDev {
-    const uint64_t* words;   // EWAH stream, zero-padded to a multiple of CHUNK words
-    const uint2* loc;        // tiles + 1 entries: (marker index, its run start) covering tile start
-    const uint64_t* mmask;   // per CHUNK words: bit j set iff word 64c + j is a marker
-    const uint32_t* mpos;    // per CHUNK words: uncompressed position where word 64c's coverage starts
+    const uint64_t* words;   // EWAH stream, zero-padded to a multiple of CHUNK words plus CHUNK more
+                             // (reads up to CHUNK words past the end stay inside the allocation)
+    const uint4* loc;        // tiles + 1 entries: {marker index, its run start, marker word lo, hi}
+                             // for the marker whose run covers the tile start
+    const uint4* desc;       // per CHUNK words c: {bit j set iff word 64c + j is a marker (lo, hi),
+                             // uncompressed position where word 64c's coverage starts, 0}
     uint32_t n_words;
     uint32_t U;              // uncompressed words
     uint64_t pad;
@@ -108,16 +112,16 @@ __host__ __device__ inline int planes_for(uint32_t n) {
     return p;
 }
 
+constexpr int WCAP = 2048;        // cooperative windows listed in LDS per round
+
 // LDS bytes needed by the tile routine for a query with N inputs.
 __host__ __device__ inline size_t tile_smem_bytes(uint32_t N) {
     size_t P = (size_t)planes_for(N);
     size_t b = P * TW * 8;                 // count planes
     b += (TW + 8) * 4;                     // one-fill difference array (+ pad)
-    b += 2 * BLOCK * 16;                   // cooperative items (two per input)
-    b += (2 * BLOCK + 8) * 4;              // window prefix
+    b += (size_t)WCAP * 16;                // window list
     b += BLOCK * 8;                        // dense row pointers
     b += 64 * 4;                           // misc counters / scan scratch
-    b += NWAVES * 64;                      // chain flags
     return b;
 }
 

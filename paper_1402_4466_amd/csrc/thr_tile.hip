@@ -122,28 +122,30 @@ struct Seg {
     bool onefull, zero;
 };
 
+// Segment of one input inside tile t from the locator entries of tiles t and
+// t + 1 alone (they carry the covering marker words).
 __device__ __forceinline__ Seg locate(const BitmapDev& B, uint32_t t, uint32_t tS, uint32_t tE, uint32_t tiles) {
     Seg s;
-    const uint2 l0 = gp(B.loc)[t];
-    uint32_t pm = l0.x, um = l0.y;
-    uint64_t h = gp(B.words)[pm];
-    uint32_t f = (uint32_t)(h & 1u), L = (uint32_t)((h >> 1) & 0xFFFFFFFFu), K = (uint32_t)(h >> 33);
-    uint32_t fa = max(um, tS), fb = min(um + L, tE);
+    const bool has_next = t + 1 < tiles;
+    const uint4 l0 = gp(B.loc)[t];
+    uint4 l1 = make_uint4(0u, 0u, 0u, 0u);
+    if (has_next) l1 = gp(B.loc)[t + 1];
+    const uint32_t pm = l0.x, um = l0.y;
+    const uint32_t f = l0.z & 1u, L = (l0.z >> 1) | (l0.w << 31), K = l0.w >> 1;
+    const uint32_t fa = max(um, tS), fb = min(um + L, tE);
     s.fa = fa; s.fb = (f && fa < fb) ? fb : fa;
-    uint32_t la = max(um + L, tS), lb = min(um + L + K, tE);
+    const uint32_t la = max(um + L, tS), lb = min(um + L + K, tE);
     s.cnt = la < lb ? lb - la : 0u;
     s.la = la;
     s.a_lit = pm + 1u + (la - (um + L));
     s.bs = pm + 1u + K;
     s.y0 = um + L + K;
     s.be = s.bs;
-    if (t + 1 < tiles) {
-        const uint2 l1 = gp(B.loc)[t + 1];
+    if (has_next) {
         if (l1.x != pm) {
-            uint64_t h2 = gp(B.words)[l1.x];
-            uint32_t L2 = (uint32_t)((h2 >> 1) & 0xFFFFFFFFu), K2 = (uint32_t)(h2 >> 33);
-            uint32_t lit_start = l1.y + L2;
-            uint32_t inlit = tE > lit_start ? min(K2, tE - lit_start) : 0u;
+            const uint32_t L2 = (l1.z >> 1) | (l1.w << 31), K2 = l1.w >> 1;
+            const uint32_t lit_start = l1.y + L2;
+            const uint32_t inlit = tE > lit_start ? min(K2, tE - lit_start) : 0u;
             s.be = l1.x + 1u + inlit;
         }
     } else if (s.bs < B.n_words) {
@@ -154,23 +156,53 @@ __device__ __forceinline__ Seg locate(const BitmapDev& B, uint32_t t, uint32_t t
     return s;
 }
 
-// One lane walks the markers of [bs, be), starting at a marker whose run starts at y0.
-__device__ __forceinline__ void walk_body(const EWT_GLOBAL uint64_t* words, uint32_t bs, uint32_t be,
-                                          uint32_t y0, uint32_t tS, uint32_t tE, uint64_t* planes,
-                                          int32_t* diff, int P) {
-    uint32_t p = bs, u = y0;
-    while (p < be && u < tE) {
-        uint64_t h = words[p];
-        uint32_t f = (uint32_t)(h & 1u), L = (uint32_t)((h >> 1) & 0xFFFFFFFFu), K = (uint32_t)(h >> 33);
-        if (f) {
-            uint32_t fa = max(u, tS), fb = min(u + L, tE);
-            if (fa < fb) { atomicAdd(&diff[fa - tS], 1); atomicAdd(&diff[fb - tS], -1); }
+// One lane decodes the compressed words [bs, be) (bs is a marker whose run
+// starts at y0) and adds whatever falls inside [tS, tE).  Words are read eight
+// at a time; streams are padded so reads up to CHUNK words past the end stay
+// inside the allocation.
+__device__ __forceinline__ void walk_lane(const EWT_GLOBAL uint64_t* words, uint32_t bs, uint32_t be, uint32_t y0,
+                                          uint32_t tS, uint32_t tE, uint64_t* planes, int32_t* diff, int P) {
+    uint32_t nm = bs;    // index of the next marker
+    uint32_t u = y0;     // run start of the next marker
+    uint32_t lb = 0;     // the dirty word at index j sits at position lb + j (mod 2^32)
+    for (uint32_t g0 = bs; g0 < be; g0 += 8u) {
+        uint64_t w[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w[i] = words[g0 + (uint32_t)i];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint32_t j = g0 + (uint32_t)i;
+            if (j < be) {
+                if (j == nm) {
+                    const uint64_t h = w[i];
+                    const uint32_t L = (uint32_t)((h >> 1) & 0xFFFFFFFFu), K = (uint32_t)(h >> 33);
+                    if (h & 1ull) {
+                        const uint32_t fa = max(u, tS), fb = min(u + L, tE);
+                        if (fa < fb) { atomicAdd(&diff[fa - tS], 1); atomicAdd(&diff[fb - tS], -1); }
+                    }
+                    lb = u + L - (j + 1u);
+                    nm = j + 1u + K;
+                    u += L + K;
+                } else {
+                    const uint32_t pos = lb + j;
+                    if (pos >= tS && pos < tE) ripple_add(planes, pos - tS, w[i], P);
+                }
+            }
         }
-        uint32_t ls = u + L;
-        uint32_t la = max(ls, tS), lb = min(ls + K, tE);
-        for (uint32_t x = la; x < lb; ++x) ripple_add(planes, x - tS, words[p + 1u + (x - ls)], P);
-        p += 1u + K;
-        u += L + K;
+    }
+}
+
+// One lane adds cnt consecutive dirty words starting at compressed index a,
+// the first at tile-relative position p0.
+__device__ __forceinline__ void lit_lane(const EWT_GLOBAL uint64_t* words, uint32_t a, uint32_t cnt, uint32_t p0,
+                                         uint64_t* planes, int P) {
+    for (uint32_t g0 = 0; g0 < cnt; g0 += 8u) {
+        uint64_t w[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w[i] = words[a + g0 + (uint32_t)i];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (g0 + (uint32_t)i < cnt) ripple_add(planes, p0 + g0 + (uint32_t)i, w[i], P);
     }
 }
 
@@ -188,17 +220,22 @@ __device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v) {
     return v;
 }
 
-// Decode one 64-word window (chunk c) of a compressed stream with one
-// wavefront.  M (bit j = word 64c + j is a marker) and uw0 (position where
-// word 64c's coverage starts) come from the skip index.  A marker covers L
-// fill words and is followed by its K dirty words, so with span = L for a
-// marker and 1 for a dirty word, each word starts at uw0 + (exclusive scan of
-// the spans): the run start for a marker, the position for a dirty word.
-__device__ __forceinline__ uint32_t decode_window(uint64_t v, uint64_t M, uint32_t uw0, bool& is_marker) {
-    const int lane = __lane_id();
-    is_marker = (M >> lane) & 1ull;
-    const uint32_t span = is_marker ? (uint32_t)((v >> 1) & 0xFFFFFFFFu) : 1u;
-    return uw0 + wave_incl_scan_dpp(span) - span;
+// Per-lane select by a wave-uniform lane mask held in scalar registers:
+// bit `lane` of mask set -> b, else a (one v_cndmask with the mask as its
+// condition operand).
+__device__ __forceinline__ uint32_t lane_sel(uint64_t mask, uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(mask));
+    return r;
+}
+__device__ __forceinline__ uint64_t lane_sel64(uint64_t mask, uint64_t a, uint64_t b) {
+    return ((uint64_t)lane_sel(mask, (uint32_t)(a >> 32), (uint32_t)(b >> 32)) << 32) |
+           lane_sel(mask, (uint32_t)a, (uint32_t)b);
+}
+// Lanes [lo, hi) of a wavefront as a mask (0 <= lo < hi <= 64).
+__device__ __forceinline__ uint64_t lane_range(uint32_t lo, uint32_t hi) {
+    const uint64_t below_hi = hi >= 64u ? ~0ull : ((1ull << hi) - 1ull);
+    return below_hi & (~0ull << lo);
 }
 
 // Exclusive prefix of the run-structure aggregate over tiles [0, t), by
@@ -269,8 +306,9 @@ __device__ Agg lookback(EWT_GLOBAL TileState* st, int t, uint32_t epoch, uint32_
 
 // ---------------------------------------------------------------- the tile
 
-// Misc LDS slots.
-constexpr int WIN_BATCH = 8;   // windows grabbed per wavefront at a time
+// Cooperative windows taken by one wavefront at a time: all their loads are
+// issued before any of them is decoded.
+constexpr int WIN_BATCH = 8;
 
 #ifdef EWT_PHASE_TIMING
 // Debug builds only: per-tile timestamps of the phase boundaries.
@@ -280,28 +318,90 @@ __device__ uint64_t* ewt_phase_buf;
 #define EWT_PHASE(k) do { } while (0)
 #endif
 
-enum { M_NITEMS = 0, M_NDENSE, M_WINCTR, M_NWIN, M_ONEFULL, M_NONZERO, M_TMP = 8, M_X = 32, M_TOT = 40 };
+// Misc LDS slots.
+enum { M_NDENSE = 1, M_ONEFULL = 4, M_NONZERO = 5, M_TMP = 8, M_X = 32, M_TOT = 40 };
+
+// Window list entry (16 bytes, one per 64-word window):
+//   x, y  address of the window's first word; bits 16..31 of y hold flags:
+//         bit 0 = aligned window of a marker-bearing range (else a block of
+//         dirty words), bits 1..6 = first lane of the range inside the window,
+//         bits 7..13 = end of the range inside the window;
+//   z, w  aligned window: address of its skip-index entry;
+//         dirty block: position of the first word (w unused).
+// A dirty block is decoded as a window without markers whose first word sits
+// at that position, so both kinds go through the same code.
+constexpr uint32_t WF_ALIGNED = 1u;
+
+__device__ __forceinline__ uint4 window_entry(const uint64_t* words, const uint4* desc, uint32_t bs, uint32_t be,
+                                              uint32_t a_lit, uint32_t cnt, uint32_t la, uint32_t nlw, uint32_t i) {
+    uint4 d;
+    if (i < nlw) {
+        const uint64_t a = (uint64_t)(uintptr_t)(words + a_lit + 64u * i);
+        const uint32_t n = min(64u, cnt - 64u * i);
+        d.x = (uint32_t)a;
+        d.y = (uint32_t)(a >> 32) | ((n << 7) << 16);
+        d.z = la + 64u * i;
+        d.w = 0u;
+    } else {
+        const uint32_t c = bs / 64u + (i - nlw);
+        const uint64_t a = (uint64_t)(uintptr_t)(words + 64u * c);
+        const uint64_t e = (uint64_t)(uintptr_t)(desc + c);
+        const uint32_t ra = max(bs, 64u * c) - 64u * c;
+        const uint32_t rb = min(be, 64u * c + 64u) - 64u * c;
+        d.x = (uint32_t)a;
+        d.y = (uint32_t)(a >> 32) | ((WF_ALIGNED | (ra << 1) | (rb << 7)) << 16);
+        d.z = (uint32_t)e;
+        d.w = (uint32_t)(e >> 32);
+    }
+    return d;
+}
+
+// Reads the list entries of windows [w0, min(w0 + WIN_BATCH, we)) (lane g holds
+// entry g), fetches the skip-index entries of aligned windows (lane g) and
+// issues the data loads of all of them; empty slots read nothing and add nothing.
+__device__ __forceinline__ void issue_batch(const uint4* win, uint32_t w0, uint32_t we, int lane, uint4& sk,
+                                            uint64_t (&v)[WIN_BATCH], uint32_t (&fl)[WIN_BATCH]) {
+    const uint32_t nb = min((uint32_t)WIN_BATCH, we - w0);
+    uint4 d = make_uint4(0u, 0u, 0u, 0u);
+    if ((uint32_t)lane < nb) d = win[w0 + (uint32_t)lane];
+    // skip-index entry of an aligned window; a dirty block has no markers and its
+    // first word at position d.z
+    sk = make_uint4(0u, 0u, d.z, 0u);
+    if ((uint32_t)lane < nb && ((d.y >> 16) & WF_ALIGNED))
+        sk = *(const EWT_GLOBAL uint4*)(uintptr_t)(((uint64_t)d.w << 32) | d.z);
+#pragma unroll
+    for (int g = 0; g < WIN_BATCH; ++g) {
+        v[g] = 0;
+        fl[g] = 0;
+        if ((uint32_t)g < nb) {
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)d.x, g);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)d.y, g);
+            fl[g] = hi >> 16;
+            const EWT_GLOBAL uint64_t* base =
+                (const EWT_GLOBAL uint64_t*)(uintptr_t)(((uint64_t)(hi & 0xFFFFu) << 32) | lo);
+            v[g] = __builtin_nontemporal_load(base + lane);
+        }
+    }
+}
 
 __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ table, uint32_t t,
                              uint32_t epoch, unsigned char* smem, uint32_t* err, uint32_t dbg_slot) {
     (void)dbg_slot;   // timestamp slot of debug builds
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wavefront
     const uint32_t N = q.N, T = q.T, U = q.U, tiles = q.tiles;
     const uint32_t tS = t * (uint32_t)TW;
     const uint32_t nPos = min((uint32_t)TW, U - tS);
     const uint32_t tE = tS + nPos;
     const int P = planes_for(N);
-    const uint32_t nb = min(N, (uint32_t)BLOCK);
     const uint32_t walk_max = (q.variant >> VAR_WALK_SHIFT) & 255u;
     const uint32_t litwalk_max = (q.variant >> VAR_LITWALK_SHIFT) & 255u;
 
     uint64_t* planes = (uint64_t*)smem;
     int32_t* diff = (int32_t*)(planes + (size_t)P * TW);
-    uint4* items = (uint4*)(diff + TW + 8);
-    uint32_t* winp = (uint32_t*)(items + 2 * BLOCK);
-    const uint64_t** dense = (const uint64_t**)(winp + 2 * BLOCK + 8);
+    uint4* win = (uint4*)(diff + TW + 8);
+    const uint64_t** dense = (const uint64_t**)(win + WCAP);
     uint32_t* misc = (uint32_t*)(dense + BLOCK);
-    (void)nb;
 
     EWT_PHASE(0);
     for (int i = tid; i < P * TW; i += BLOCK) planes[i] = 0;
@@ -312,14 +412,16 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     // ---- classify / prune (RBMrg on EWAH, cases 1 and 2, per tile)
     const bool trivial = (T == 0) || (T > N);
     Seg seg;
+    BitmapDev B0;
     if (!trivial) {
         for (uint32_t kb = 0; kb < N; kb += BLOCK) {
             uint32_t k = kb + (uint32_t)tid;
             if (k < N) {
-                Seg s = locate(gp(table)[gp(q.ids)[k]], t, tS, tE, tiles);
+                const BitmapDev B = gp(table)[gp(q.ids)[k]];
+                Seg s = locate(B, t, tS, tE, tiles);
                 if (s.onefull) atomicAdd(&misc[M_ONEFULL], 1u);
                 if (!s.zero) atomicAdd(&misc[M_NONZERO], 1u);
-                if (kb == 0) seg = s;
+                if (kb == 0) { seg = s; B0 = B; }
             }
         }
     }
@@ -331,173 +433,129 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     // ---- decode and count
     if (mode == 0) {
         for (uint32_t kb = 0; kb < N; kb += BLOCK) {
-            uint32_t k = kb + (uint32_t)tid;
+            const uint32_t k = kb + (uint32_t)tid;
+            uint32_t nlw = 0, nww = 0;
+            Seg s = {};
+            const uint64_t* wp = nullptr;
+            const uint4* dp = nullptr;
             if (k < N) {
-                const uint32_t slot = gp(q.ids)[k];
-                const BitmapDev B = gp(table)[slot];
-                Seg s = (kb == 0) ? seg : locate(B, t, tS, tE, tiles);
+                BitmapDev B = B0;
+                if (kb != 0) B = gp(table)[gp(q.ids)[k]];
+                s = (kb == 0) ? seg : locate(B, t, tS, tE, tiles);
+                wp = B.words;
+                dp = B.desc;
                 if (s.fa < s.fb) { atomicAdd(&diff[s.fa - tS], 1); atomicAdd(&diff[s.fb - tS], -1); }
                 if (s.cnt) {
                     if ((q.variant & VAR_DENSE) && s.cnt == nPos) {
                         uint32_t j = atomicAdd(&misc[M_NDENSE], 1u);
-                        dense[j] = B.words + s.a_lit;
+                        dense[j] = wp + s.a_lit;
                     } else if (s.cnt <= litwalk_max) {
-                        for (uint32_t j = 0; j < s.cnt; ++j) ripple_add(planes, s.la - tS + j, gp(B.words)[s.a_lit + j], P);
+                        lit_lane(gp(wp), s.a_lit, s.cnt, s.la - tS, planes, P);
                     } else {
-                        uint32_t j = atomicAdd(&misc[M_NITEMS], 1u);
-                        items[j] = make_uint4(slot, s.a_lit, s.a_lit + s.cnt, s.la | 0x80000000u);
+                        nlw = (s.cnt + 63u) / 64u;
                     }
                 }
                 if (s.be > s.bs) {
-                    if (s.be - s.bs <= walk_max) {
-                        walk_body(gp(B.words), s.bs, s.be, s.y0, tS, tE, planes, diff, P);
-                    } else {
-                        uint32_t j = atomicAdd(&misc[M_NITEMS], 1u);
-                        items[j] = make_uint4(slot, s.bs, s.be, 0u);
-                    }
+                    if (s.be - s.bs <= walk_max) walk_lane(gp(wp), s.bs, s.be, s.y0, tS, tE, planes, diff, P);
+                    else nww = (s.be - 1u) / 64u - s.bs / 64u + 1u;
                 }
             }
-            __syncthreads();
             EWT_PHASE(2);
-            // window prefix over the cooperative items (two per thread)
-            const uint32_t n_items = misc[M_NITEMS];
-            uint32_t w2[2] = {0u, 0u};
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                uint32_t i = 2u * (uint32_t)tid + (uint32_t)h;
-                if (i < n_items) {
-                    uint4 it = items[i];
-                    w2[h] = (it.w & 0x80000000u) ? (it.z - it.y + 63u) / 64u : ((it.z - 1u) / 64u - it.y / 64u + 1u);
-                }
-            }
+            // window offsets of every input (block scan); the windows are then
+            // listed and processed in rounds of at most WCAP
             uint32_t tot;
-            uint32_t ex = block_excl_scan(w2[0] + w2[1], misc + M_TMP, tot);
-            if (2u * (uint32_t)tid < n_items) winp[2 * tid] = ex;
-            if (2u * (uint32_t)tid + 1u < n_items) winp[2 * tid + 1] = ex + w2[0];
-            if (tid == 0) { misc[M_NWIN] = tot; misc[M_WINCTR] = 0; }
-            __syncthreads();
+            const uint32_t off = block_excl_scan(nlw + nww, misc + M_TMP, tot);
+            for (uint32_t j = off; j < min(off + nlw + nww, (uint32_t)WCAP); ++j)
+                win[j] = window_entry(wp, dp, s.bs, s.be, s.a_lit, s.cnt, s.la, nlw, j - off);
+            for (uint32_t W0 = 0; W0 < tot; W0 += (uint32_t)WCAP) {
+                const uint32_t nr = min((uint32_t)WCAP, tot - W0);
+                if (W0 > 0) {   // later rounds (long tiles): the segment is located again
+                    const uint32_t j0 = max(off, W0), j1 = min(off + nlw + nww, W0 + nr);
+                    if (j0 < j1) {
+                        const BitmapDev B = gp(table)[gp(q.ids)[k]];
+                        const Seg s2 = locate(B, t, tS, tE, tiles);
+                        for (uint32_t j = j0; j < j1; ++j)
+                            win[j - W0] = window_entry(B.words, B.desc, s2.bs, s2.be, s2.a_lit, s2.cnt, s2.la, nlw, j - off);
+                    }
+                }
+                __syncthreads();
 
-            // cooperative windows: one wavefront per 64 compressed words, WIN_BATCH
-            // windows per grab, all loads issued before any decoding and the
-            // ripple adds of the batch interleaved
-            const uint32_t total_w = misc[M_NWIN];
-            while (true) {
-                uint32_t w0 = 0;
-                if (lane == 0) w0 = atomicAdd(&misc[M_WINCTR], (uint32_t)WIN_BATCH);
-                w0 = __builtin_amdgcn_readfirstlane(__shfl(w0, 0, 64));
-                if (w0 >= total_w) break;
-                uint32_t lo = 0, hi = n_items - 1;       // largest i with winp[i] <= w0
-                while (lo < hi) {
-                    uint32_t mid = (lo + hi + 1) >> 1;
-                    if (winp[mid] <= w0) lo = mid; else hi = mid - 1;
-                }
-                lo = __builtin_amdgcn_readfirstlane(lo);
-                uint32_t wi = __builtin_amdgcn_readfirstlane(w0 - winp[lo]);
-                uint32_t lo_n = __builtin_amdgcn_readfirstlane(((lo + 1 < n_items) ? winp[lo + 1] : total_w) - winp[lo]);
-                uint64_t vs[WIN_BATCH];
-                uint64_t ms[WIN_BATCH];
-                uint32_t ps[WIN_BATCH];
-                uint4 its[WIN_BATCH];
-                uint32_t qs[WIN_BATCH];
-                uint32_t wis[WIN_BATCH];
-                // stage 1: which item and window each batch slot is (wave-uniform)
-#pragma unroll
-                for (int g = 0; g < WIN_BATCH; ++g) {
-                    if (g > 0) {
-                        if (wi + 1u >= lo_n && lo + 1 < n_items) {
-                            ++lo;
-                            wi = 0;
-                            lo_n = __builtin_amdgcn_readfirstlane(((lo + 1 < n_items) ? winp[lo + 1] : total_w) - winp[lo]);
-                        } else {
-                            ++wi;
-                        }
-                    }
-                    uint4 it = items[lo];
-                    it.x = __builtin_amdgcn_readfirstlane(it.x);
-                    it.y = __builtin_amdgcn_readfirstlane(it.y);
-                    it.z = __builtin_amdgcn_readfirstlane(it.z);
-                    it.w = __builtin_amdgcn_readfirstlane(it.w);
-                    its[g] = it;
-                    wis[g] = wi;
-                }
-                // stage 2: descriptors of the bitmaps involved (scalar loads)
-                const uint64_t* wpt[WIN_BATCH];
-                const uint64_t* mpt[WIN_BATCH];
-                const uint32_t* ppt[WIN_BATCH];
-#pragma unroll
-                for (int g = 0; g < WIN_BATCH; ++g) {
-                    const EWT_GLOBAL BitmapDev* B = gp(table) + its[g].x;
-                    wpt[g] = B->words;
-                    mpt[g] = B->mmask;
-                    ppt[g] = B->mpos;
-                }
-                // stage 3: all data loads of the batch
-#pragma unroll
-                for (int g = 0; g < WIN_BATCH; ++g) {
-                    const uint4 it = its[g];
-                    vs[g] = 0;
-                    ms[g] = 0;
-                    ps[g] = 0;
-                    qs[g] = 0;
-                    if (w0 + (uint32_t)g < total_w) {
-                        if (it.w & 0x80000000u) {
-                            const uint32_t qv = it.y + wis[g] * 64u + (uint32_t)lane;
-                            qs[g] = qv;
-                            if (qv < it.z) vs[g] = __builtin_nontemporal_load(gp(wpt[g]) + qv);
-                        } else {
-                            const uint32_t c = (it.y >> 6) + wis[g];
-                            const uint32_t qv = c * 64u + (uint32_t)lane;
-                            qs[g] = qv;
-                            vs[g] = __builtin_nontemporal_load(gp(wpt[g]) + qv);
-                            ms[g] = gp(mpt[g])[c];
-                            ps[g] = gp(ppt[g])[c];
-                        }
-                    }
-                }
-                // decode: position of every dirty word in the tile (or no add)
-                uint32_t rp[WIN_BATCH];
-#pragma unroll
-                for (int g = 0; g < WIN_BATCH; ++g) {
-                    const uint4 it = its[g];
-                    const uint32_t qv = qs[g];
-                    uint64_t v = vs[g];
-                    uint32_t r = 0;
-                    if (w0 + (uint32_t)g >= total_w) {
-                        v = 0;
-                    } else if (it.w & 0x80000000u) {
-                        if (qv < it.z) r = (it.w & 0x7FFFFFFFu) + (qv - it.y) - tS;
-                        else v = 0;
-                    } else {
-                        bool im;
-                        const uint32_t pos = decode_window(v, ms[g], ps[g], im);
-                        const bool in = qv >= it.y && qv < it.z;
-                        if (in && im && (v & 1ull)) {
-                            const uint32_t L = (uint32_t)((v >> 1) & 0xFFFFFFFFu);
-                            const uint32_t fa = max(pos, tS), fb = min(pos + L, tE);
-                            if (fa < fb) { atomicAdd(&diff[fa - tS], 1); atomicAdd(&diff[fb - tS], -1); }
-                        }
-                        if (in && !im && pos >= tS && pos < tE) r = pos - tS;
-                        else v = 0;
-                    }
-                    vs[g] = v;
-                    rp[g] = r;
-                }
-                // interleaved ripple-carry adds of the batch
-                for (int p = 0; p < P; ++p) {
-                    uint64_t any = 0;
+                // each wavefront takes a contiguous share of the round's windows
+                const uint32_t wb = (nr * (uint32_t)wave) / NWAVES, we = (nr * (uint32_t)(wave + 1)) / NWAVES;
+                // software pipeline: the loads of batch k + 1 are in flight while batch k
+                // is added into the planes
+                uint4 sk;
+                uint64_t v[WIN_BATCH];
+                uint32_t fl[WIN_BATCH];
+                issue_batch(win, wb, we, lane, sk, v, fl);
+                for (uint32_t w0 = wb; w0 < we; w0 += (uint32_t)WIN_BATCH) {
+                    // decode, branch-free over the batch: position of every word (span = L
+                    // for a marker, 1 for a dirty word)
+                    uint32_t r[WIN_BATCH];
+                    uint64_t x[WIN_BATCH], fills[WIN_BATCH], lit[WIN_BATCH];
+                    uint32_t any_fill = 0;
 #pragma unroll
                     for (int g = 0; g < WIN_BATCH; ++g) {
-                        if (vs[g]) {
-                            const uint64_t old = atomicXor((unsigned long long*)&planes[p * TW + rp[g]],
-                                                           (unsigned long long)vs[g]);
-                            vs[g] &= old;
-                        }
-                        any |= vs[g];
+                        const uint32_t m0 = (uint32_t)__builtin_amdgcn_readlane((int)sk.x, g);
+                        const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)sk.y, g);
+                        const uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)sk.z, g);
+                        const uint64_t M = ((uint64_t)m1 << 32) | m0;
+                        const uint64_t inr = lane_range((fl[g] >> 1) & 63u, (fl[g] >> 7) & 127u);
+                        x[g] = v[g];
+                        const uint32_t span = lane_sel(M, 1u, (uint32_t)(x[g] >> 1));
+                        r[g] = p0 + wave_incl_scan_dpp(span) - span;
+                        fills[g] = __ballot((uint32_t)x[g] & 1u) & M & inr;
+                        lit[g] = ~M & inr & __ballot(r[g] >= tS) & __ballot(r[g] < tE);
+                        any_fill |= fills[g] ? (1u << g) : 0u;
                     }
-                    if (!__any(any != 0)) break;
+                    // one-fills of markers in range (rare): counted through the difference array
+                    if (any_fill) {
+#pragma unroll
+                        for (int g = 0; g < WIN_BATCH; ++g) {
+                            if (((any_fill >> g) & 1u) && ((fills[g] >> lane) & 1ull)) {
+                                const uint32_t L = (uint32_t)(x[g] >> 1);
+                                const uint32_t fa = max(r[g], tS), fb = min(r[g] + L, tE);
+                                if (fa < fb) { atomicAdd(&diff[fa - tS], 1); atomicAdd(&diff[fb - tS], -1); }
+                            }
+                        }
+                    }
+                    // dirty words in range add at their tile-relative position
+                    uint32_t act = 0;   // bit g: window g still carries somewhere
+#pragma unroll
+                    for (int g = 0; g < WIN_BATCH; ++g) {
+                        r[g] -= tS;
+                        x[g] = lane_sel64(lit[g], 0ull, x[g]);
+                        if (lit[g]) act |= 1u << g;
+                    }
+                    // next batch's loads
+                    if (w0 + (uint32_t)WIN_BATCH < we) issue_batch(win, w0 + (uint32_t)WIN_BATCH, we, lane, sk, v, fl);
+                    // ripple-carry adds, one plane at a time: all atomics of a plane are
+                    // issued before any result is used; a window drops out once none of
+                    // its lanes carries
+                    for (int p = 0; p < P && act; ++p) {
+                        uint64_t old[WIN_BATCH];
+#pragma unroll
+                        for (int g = 0; g < WIN_BATCH; ++g) {
+                            old[g] = 0;
+                            if (act & (1u << g))
+                                old[g] = atomicXor((unsigned long long*)&planes[p * TW + r[g]], (unsigned long long)x[g]);
+                        }
+                        // one wait for all of them (lgkmcnt(0)); without it the compiler cannot tell
+                        // that no result is still in flight at the next plane and waits per atomic
+                        __builtin_amdgcn_s_waitcnt(0xC07F);
+                        uint32_t nact = 0;
+#pragma unroll
+                        for (int g = 0; g < WIN_BATCH; ++g) {
+                            if (act & (1u << g)) {
+                                x[g] &= old[g];
+                                if (__ballot(x[g] != 0ull)) nact |= 1u << g;
+                            }
+                        }
+                        act = nact;
+                    }
                 }
+                __syncthreads();
             }
-            __syncthreads();
 
             EWT_PHASE(3);
             // dense rows: Harley-Seal carry-save-adder tree, one lane per word position
@@ -506,11 +564,11 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                 uint64_t R[MAXP];
 #pragma unroll
                 for (int p = 0; p < MAXP; ++p) R[p] = 0;
-                uint32_t d = 0;
-                for (; d + 16u <= n_dense; d += 16u) {
+                for (uint32_t d = 0; d < n_dense; d += 16u) {   // a short last group reads zeros
                     uint64_t x[16];
 #pragma unroll
-                    for (int j = 0; j < 16; ++j) x[j] = __builtin_nontemporal_load(gp(dense[d + j]) + tid);
+                    for (int j = 0; j < 16; ++j)
+                        x[j] = d + (uint32_t)j < n_dense ? __builtin_nontemporal_load(gp(dense[d + j]) + tid) : 0ull;
                     uint64_t twosA, twosB, foursA, foursB, eightsA, eightsB, sixteens;
                     EWT_CSA(twosA, R[0], R[0], x[0], x[1]);
                     EWT_CSA(twosB, R[0], R[0], x[2], x[3]);
@@ -531,11 +589,6 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
 #pragma unroll
                     for (int p = 4; p < MAXP; ++p) { uint64_t tt = R[p] & cy; R[p] ^= cy; cy = tt; }
                 }
-                for (; d < n_dense; ++d) {
-                    uint64_t cy = __builtin_nontemporal_load(gp(dense[d]) + tid);
-#pragma unroll
-                    for (int p = 0; p < MAXP; ++p) { uint64_t tt = R[p] & cy; R[p] ^= cy; cy = tt; }
-                }
                 uint64_t cy = 0;
 #pragma unroll
                 for (int p = 0; p < MAXP; ++p) {
@@ -548,7 +601,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                 }
             }
             __syncthreads();
-            if (tid == 0) { misc[M_NITEMS] = 0; misc[M_NDENSE] = 0; }
+            if (tid == 0) misc[M_NDENSE] = 0;
             __syncthreads();
         }
     }
