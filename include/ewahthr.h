@@ -149,7 +149,7 @@ typedef struct {
 } ewah_query;
 
 typedef struct {
-    uint32_t grid;          /* persistent workgroups, 0 = one per compute unit */
+    uint32_t grid;          /* persistent workgroups, 0 = all that can be resident at once */
     int use_graph;          /* 1 = capture bump + persistent kernel into a hipGraph */
 } ewah_batch_config;
 

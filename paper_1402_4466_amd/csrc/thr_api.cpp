@@ -571,7 +571,7 @@ ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, con
     HIPCHK(hipMalloc(&b->d_qs, nq * sizeof(QueryDev)));
     HIPCHK(hipMemcpy(b->d_qs, b->h_qs.data(), nq * sizeof(QueryDev), hipMemcpyHostToDevice));
     b->smem = tile_smem_bytes(maxN);
-    b->grid = (cfg && cfg->grid) ? cfg->grid : g.n_cu;
+    b->grid = (cfg && cfg->grid) ? cfg->grid : g.n_cu * (uint32_t)batch_blocks_per_cu(b->smem);
     b->use_graph = cfg ? cfg->use_graph : 1;
     st = batch_build_graph(b.get());
     if (st) return st;

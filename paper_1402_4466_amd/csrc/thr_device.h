@@ -42,8 +42,11 @@
 
 namespace ewt {
 
-constexpr int TW = 1024;          // tile width in uncompressed 64-bit words (= locator granularity)
-constexpr int BLOCK = 1024;       // threads per workgroup (one per word position of a tile)
+#ifndef EWT_TILE_WORDS
+#define EWT_TILE_WORDS 1024       // compile-time tile width (host and device must agree)
+#endif
+constexpr int TW = EWT_TILE_WORDS;    // tile width in uncompressed 64-bit words (= locator granularity)
+constexpr int BLOCK = EWT_TILE_WORDS; // threads per workgroup (one per word position of a tile)
 constexpr int NWAVES = BLOCK / 64;
 constexpr int CHUNK = 64;         // compressed words per skip-index entry (one wavefront)
 constexpr int MAXP = 12;          // bit planes: inputs per query < 2^12 (LDS budget)
@@ -112,7 +115,7 @@ __host__ __device__ inline int planes_for(uint32_t n) {
     return p;
 }
 
-constexpr int WCAP = 2048;        // cooperative windows listed in LDS per round
+constexpr int WCAP = 2 * BLOCK;   // cooperative windows listed in LDS per round
 
 // LDS bytes needed by the tile routine for a query with N inputs.
 __host__ __device__ inline size_t tile_smem_bytes(uint32_t N) {
@@ -133,6 +136,7 @@ hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, uint32_t nq, 
 hipError_t launch_bump(uint32_t* epoch, hipStream_t s);
 hipError_t launch_zero_len(uint64_t* out_n, hipStream_t s);
 hipError_t set_smem_limits(size_t max_bytes);
+int batch_blocks_per_cu(size_t smem);   // resident workgroups of the batched kernel per CU
 hipError_t launch_features(const QueryDev* qs, uint32_t nq, const float4* stats, float r, float* feat, hipStream_t s);
 hipError_t launch_select(const float* pred, uint32_t nq, uint32_t n_arms, const uint32_t* codes, QueryDev* qs,
                          hipStream_t s);

@@ -739,10 +739,12 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
 }
 
 // ----------------------------------------------------------------- kernels
+// Both kernels are built for four wavefronts per SIMD (at most 128 VGPRs), so a
+// compute unit holds 1024 threads: one workgroup of 1024 or two of 512.
 
 // One query, one workgroup per tile.  Tiles are taken in ticket order so that a
 // tile only ever waits for tiles that are already running or done.
-__global__ __launch_bounds__(BLOCK) void thr_query_kernel(QueryDev q, const BitmapDev* __restrict__ table,
+__global__ __launch_bounds__(BLOCK, 4) void thr_query_kernel(QueryDev q, const BitmapDev* __restrict__ table,
                                                           uint32_t* ticket, uint32_t epoch, uint32_t* err) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_t;
@@ -757,7 +759,7 @@ __global__ __launch_bounds__(BLOCK) void thr_query_kernel(QueryDev q, const Bitm
 
 // Many queries in one persistent launch: workgroups take (query, tile) items
 // from a global counter in order.  qtile[i] = first item of query i (qtile[nq] = total).
-__global__ __launch_bounds__(BLOCK) void thr_batch_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
+__global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
                                                           uint32_t nq, const BitmapDev* __restrict__ table,
                                                           uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -809,6 +811,12 @@ hipError_t set_smem_limits(size_t max_bytes) {
     hipError_t e = hipFuncSetAttribute((const void*)thr_query_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)thr_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
+}
+
+int batch_blocks_per_cu(size_t smem) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)thr_batch_kernel, BLOCK, smem) != hipSuccess) return 1;
+    return n > 0 ? n : 1;
 }
 
 hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* ticket, uint32_t epoch, uint32_t* err,

@@ -1,0 +1,148 @@
+"""Parity at the full workload sizes, in the launch configurations the benchmark times
+(needs an MI355X).
+
+* N=64 Markov bitmaps over 2^24 rows and N=1024 Zipf-density bitmaps over 2^26
+  rows: every output word of every threshold compared with the oracle (the
+  oracle finishes these in seconds);
+* the batched workload (pool of 10,000 bitmaps over 2^22 rows, 4,096 queries)
+  in the benchmark's launch: learned variant selection on the device, the tuned
+  persistent grid, one graph launch.  Sampled queries are compared whole with
+  the oracle; every other output is checked for properties that hold at any
+  size: it decodes to exactly U words, it is canonical (re-encoding it gives it
+  back), and its length respects the output bound;
+* degenerate shapes and the input-count limit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1402_4466_amd import datagen as D
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def G():
+    from tests import gpu_util
+    gpu_util.lib()
+    return gpu_util
+
+
+def _plain_all_T(G, w, variants):
+    E = G.lib()
+    bms = G.register(w.streams, w.n_bits)
+    try:
+        for q in w.queries:
+            want, _ = O.threshold([w.streams[i] for i in q.idx], w.n_bits, q.T, want_hist=False)
+            for v in variants:
+                got = G.gpu_threshold([bms[i] for i in q.idx], q.T, variant=v)
+                _say(f"{w.name} T={q.T} variant={v:#x}: {len(got)} words (oracle {len(want)})")
+                assert np.array_equal(got, want), (w.name, q.T, v)
+    finally:
+        for b in bms:
+            b.release()
+    assert E.device_errors() == 0
+
+
+def test_config2_full(G):
+    E = G.lib()
+    _plain_all_T(G, D.config2(), [0, E.variant_code(False, 0, 0)])
+
+
+def test_config3_full(G):
+    _plain_all_T(G, D.config3(), [0])
+
+
+def test_batched_full_size_sampled(G):
+    import torch
+    E = G.lib()
+    from paper_1402_4466_amd import autotune as A
+    from paper_1402_4466_amd import selector as S
+    n_bits = 1 << 22
+    U = n_bits // 64
+    pool, _ = D.config4_pool(10_000)
+    qs = D.queries(D.SEED_BASE + 4, 4096, 10_000, 2, 256)
+    bms = E.register_many(pool, n_bits)
+    nw = np.array([len(s) for s in pool], dtype=np.int64)
+    caps = [E.output_bound(n_bits, int(nw[q.idx].sum())) for q in qs]
+    offs = np.concatenate([[0], np.cumsum(caps)])
+    out = torch.zeros(int(offs[-1]), dtype=torch.int64, device="cuda")
+    out_n = torch.zeros(len(qs), dtype=torch.int64, device="cuda")
+    batch = E.Batch(bms, [(q.idx, q.T) for q in qs], [out.data_ptr() + 8 * int(o) for o in offs[:-1]], caps,
+                    [out_n.data_ptr() + 8 * i for i in range(len(qs))], grid=E.num_cus(), use_graph=True)
+    sel = S.load_selector()
+    kind = sel.apply(batch, bms, qs, n_bits)
+    tuned = A.lookup(f"c4_q{len(qs)}_pool{len(pool)}_{kind}")
+    batch.set_grid(int(tuned["grid"]) if tuned else E.num_cus())
+    batch.run()
+    torch.cuda.synchronize()
+    assert E.device_errors() == 0
+    ns = out_n.cpu().numpy()
+    host = out.cpu().numpy().view(np.uint64)
+    rng = np.random.default_rng(2024)
+    sample = set(rng.choice(len(qs), 12, replace=False).tolist()) | {int(np.argmax([len(q.idx) for q in qs]))}
+    for i, q in enumerate(qs):
+        got = host[offs[i]:offs[i] + ns[i]]
+        assert 0 < ns[i] <= caps[i], (i, ns[i], caps[i])
+        if i in sample:
+            want, _ = O.threshold([pool[j] for j in q.idx], n_bits, q.T, want_hist=False)
+            _say(f"query {i}: N={len(q.idx)} T={q.T}: {len(got)} words (oracle {len(want)})")
+            assert np.array_equal(got, want), i
+        else:
+            dense = O.decode(got, n_bits)
+            assert len(dense) == U
+            assert np.array_equal(O.encode(dense, n_bits), got), i
+    batch.free()
+    for b in bms:
+        b.release()
+
+
+def test_degenerate_shapes(G):
+    E = G.lib()
+    rng = np.random.default_rng(77)
+    for n_bits in (1, 63, 64, 65, 64 * 1024, 64 * 1024 + 1, 64 * 2048 - 1):
+        U = (n_bits + 63) // 64
+        zeros = np.zeros(U, dtype=np.uint64)
+        ones = np.full(U, ~np.uint64(0), dtype=np.uint64)
+        rnd = rng.integers(0, 2**63, U, dtype=np.uint64) | rng.integers(0, 2, U, dtype=np.uint64) << np.uint64(63)
+        streams = [O.encode(x, n_bits) for x in (zeros, ones, rnd)]
+        bms = G.register(streams, n_bits)
+        try:
+            for sub in ([0], [1], [2], [0, 1], [1, 2], [0, 1, 2], [1, 1, 2, 2]):
+                ins = [bms[i] for i in sub]
+                for T in range(0, len(sub) + 2):
+                    want, _ = O.threshold([streams[i] for i in sub], n_bits, T, want_hist=False)
+                    got = G.gpu_threshold(ins, T)
+                    assert np.array_equal(got, want), (n_bits, sub, T)
+        finally:
+            for b in bms:
+                b.release()
+    assert E.device_errors() == 0
+
+
+def test_input_count_limit(G):
+    E = G.lib()
+    n_bits = 2 * 64 * 1024 + 333
+    n = 4095   # largest query the planes admit
+    dens = np.full(n, 0.002)
+    streams = D.bitmaps(D.IID, dens, 0.0, n_bits, [D.key(4095, k) for k in range(n)])
+    bms = G.register(streams, n_bits)
+    try:
+        for T in (1, 2, 3, 4095):
+            want, _ = O.threshold(streams, n_bits, T, want_hist=False)
+            got = G.gpu_threshold(bms, T)
+            assert np.array_equal(got, want), T
+        out, out_n, cap = G.alloc_out(n_bits, sum(len(s) for s in streams) * 2)
+        with pytest.raises(E.EwahError) as e:
+            E.threshold(bms + bms[:1], 1, out.data_ptr(), cap, out_n.data_ptr())
+        assert e.value.code == E.EINVAL
+    finally:
+        for b in bms:
+            b.release()
+    assert E.device_errors() == 0
