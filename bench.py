@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--selector", default=None, help="variant selector file (default: autotune cache if present)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--tune", action="store_true", help="run the autotuner if no cached entry exists")
+    ap.add_argument("--retune", action="store_true", help="tune the persistent grid even if a cached choice exists")
     return ap.parse_args()
 
 
@@ -137,8 +138,8 @@ def bench_c4(args, E, torch):
         batch.run(stream)                # one persistent, graph-captured launch of every query
 
     signature = f"c4_q{len(qs)}_pool{len(pool)}_{sel_kind}"
-    tuned = A.lookup(signature)
-    if tuned is None and args.tune:
+    tuned = None if args.retune else A.lookup(signature)
+    if tuned is None and (args.tune or args.retune):
         tuned = A.tune_batch(batch, step, signature, E.num_cus(), log=log)
     grid = int(tuned["grid"]) if tuned else E.num_cus()
     batch.set_grid(grid)

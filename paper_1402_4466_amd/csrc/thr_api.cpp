@@ -86,8 +86,18 @@ ewah_status ensure_ready() {
 struct Built {
     std::vector<uint4> loc;    // per tile boundary: covering marker index, its run start, the marker word
     std::vector<uint4> desc;   // per CHUNK words: marker mask (lo, hi), position of the chunk's first word
+    std::vector<uint4> pres;   // per tile: groups of GW words holding a dirty word or a one-fill
     ewah_stats st{};
 };
+
+// Sets bits [lo, hi] of a bit vector.
+void set_bits(std::vector<uint64_t>& v, uint64_t lo, uint64_t hi) {
+    for (uint64_t w = lo / 64; w <= hi / 64; ++w) {
+        const uint64_t a = (w == lo / 64) ? lo % 64 : 0, b = (w == hi / 64) ? hi % 64 : 63;
+        const uint64_t m = (b == 63 ? ~0ull : ((1ull << (b + 1)) - 1)) & (~0ull << a);
+        v[w] |= m;
+    }
+}
 
 inline uint64_t popc64(uint64_t x) { return (uint64_t)__builtin_popcountll(x); }
 
@@ -99,6 +109,7 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
     const uint64_t tiles = (U + TW - 1) / TW;
     const uint64_t nchunks = (nw + CHUNK - 1) / CHUNK;
     b.loc.assign(tiles + 1, make_uint4(0, 0, 0, 0));
+    std::vector<uint64_t> gbits((tiles * NGROUPS + 63) / 64 + 1, 0);   // presence groups of the whole bitmap
     b.desc.assign(nchunks, make_uint4(0, 0, 0, 0));
     const uint64_t tailmask = (n_bits % 64) ? ((1ull << (n_bits % 64)) - 1) : ~0ull;
     ewah_stats& st = b.st;
@@ -128,6 +139,8 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
         if (bit < 32) b.desc[c].x |= 1u << bit;
         else b.desc[c].y |= 1u << (bit - 32);
         if (p % CHUNK == 0) b.desc[c].z = (uint32_t)u;
+        if (f && L) set_bits(gbits, u / GW, (u + L - 1) / GW);
+        if (K) set_bits(gbits, (u + L) / GW, (u + L + K - 1) / GW);
         if (L + K > 0) {
             const uint4 e = make_uint4((uint32_t)p, (uint32_t)u, (uint32_t)m, (uint32_t)(m >> 32));
             for (uint64_t t = (u + TW - 1) / TW; t * TW < u + L + K && t < tiles; ++t) b.loc[t] = e;
@@ -161,7 +174,16 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
     }
     if (u != U) return fail(EWAH_EFORMAT, "stream covers " + std::to_string(u) + " words, expected " + std::to_string(U));
     if (tiles) b.loc[tiles] = make_uint4((uint32_t)nw, (uint32_t)U, 0, 0);
-    st.index_bytes = b.loc.size() * sizeof(uint4) + b.desc.size() * sizeof(uint4);
+    b.pres.assign(tiles, make_uint4(0, 0, 0, 0));
+    for (uint64_t t = 0; t < tiles; ++t) {
+        uint32_t q[4] = {0, 0, 0, 0};
+        for (int k = 0; k < NGROUPS / 32; ++k) {
+            const uint64_t g0 = t * NGROUPS + 32 * (uint64_t)k;   // 32-aligned: within one 64-bit word
+            q[k] = (uint32_t)(gbits[g0 / 64] >> (g0 % 64));
+        }
+        b.pres[t] = make_uint4(q[0], q[1], q[2], q[3]);
+    }
+    st.index_bytes = (b.loc.size() + b.desc.size() + b.pres.size()) * sizeof(uint4);
     return EWAH_OK;
 }
 
@@ -305,7 +327,7 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
     // skip index | locator], each part 256-byte aligned.  The image is assembled on the host
     // and uploaded in pieces of at most kStage bytes.
     constexpr size_t kStage = 256ull << 20;
-    struct Layout { size_t words, desc, loc, end; };
+    struct Layout { size_t words, desc, loc, pres, end; };
     std::vector<Layout> lay(count);
     size_t total = 0;
     for (uint32_t i = 0; i < count; ++i) {
@@ -314,7 +336,8 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
         l.words = total;
         l.desc = l.words + align256((nch * CHUNK + CHUNK) * 8);
         l.loc = l.desc + align256(nch * 16);
-        l.end = l.loc + align256(built[i].loc.size() * 16);
+        l.pres = l.loc + align256(built[i].loc.size() * 16);
+        l.end = l.pres + align256(std::max<size_t>(built[i].pres.size(), 1) * 16);
         total = l.end;
     }
     Arena* arena = new Arena();
@@ -339,6 +362,8 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
             if (!built[i].desc.empty())
                 std::memcpy(stage.data() + (lay[i].desc - base), built[i].desc.data(), built[i].desc.size() * 16);
             std::memcpy(stage.data() + (lay[i].loc - base), built[i].loc.data(), built[i].loc.size() * 16);
+            if (!built[i].pres.empty())
+                std::memcpy(stage.data() + (lay[i].pres - base), built[i].pres.data(), built[i].pres.size() * 16);
         }
         HIPCHK(hipMemcpy((char*)arena->d + base, stage.data(), len, hipMemcpyHostToDevice));
         i0 = i1;
@@ -349,7 +374,7 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
         b->dev.words = (const uint64_t*)(base + lay[i].words);
         b->dev.loc = (const uint4*)(base + lay[i].loc);
         b->dev.desc = (const uint4*)(base + lay[i].desc);
-        b->dev.pad = 0;
+        b->dev.pres = (const uint4*)(base + lay[i].pres);
         b->dev.n_words = (uint32_t)v[i].n_words;
         b->dev.U = (uint32_t)((v[i].n_bits + 63) / 64);
         b->stats = built[i].st;

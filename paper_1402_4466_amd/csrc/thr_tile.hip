@@ -160,8 +160,12 @@ __device__ __forceinline__ Seg locate(const BitmapDev& B, uint32_t t, uint32_t t
 // starts at y0) and adds whatever falls inside [tS, tE).  Words are read eight
 // at a time; streams are padded so reads up to CHUNK words past the end stay
 // inside the allocation.
+__device__ __forceinline__ bool pruned_at(const uint4& pm, uint32_t rel);
+
 __device__ __forceinline__ void walk_lane(const EWT_GLOBAL uint64_t* words, uint32_t bs, uint32_t be, uint32_t y0,
-                                          uint32_t tS, uint32_t tE, uint64_t* planes, int32_t* diff, int P) {
+                                          uint32_t tS, uint32_t tE, uint64_t* planes, int32_t* diff, int P,
+                                          const uint4& pm) {
+    const bool prune = (pm.x | pm.y | pm.z | pm.w) != 0u;
     uint32_t nm = bs;    // index of the next marker
     uint32_t u = y0;     // run start of the next marker
     uint32_t lb = 0;     // the dirty word at index j sits at position lb + j (mod 2^32)
@@ -185,7 +189,7 @@ __device__ __forceinline__ void walk_lane(const EWT_GLOBAL uint64_t* words, uint
                     u += L + K;
                 } else {
                     const uint32_t pos = lb + j;
-                    if (pos >= tS && pos < tE) ripple_add(planes, pos - tS, w[i], P);
+                    if (pos >= tS && pos < tE && !(prune && pruned_at(pm, pos - tS))) ripple_add(planes, pos - tS, w[i], P);
                 }
             }
         }
@@ -195,14 +199,16 @@ __device__ __forceinline__ void walk_lane(const EWT_GLOBAL uint64_t* words, uint
 // One lane adds cnt consecutive dirty words starting at compressed index a,
 // the first at tile-relative position p0.
 __device__ __forceinline__ void lit_lane(const EWT_GLOBAL uint64_t* words, uint32_t a, uint32_t cnt, uint32_t p0,
-                                         uint64_t* planes, int P) {
+                                         uint64_t* planes, int P, const uint4& pm) {
+    const bool prune = (pm.x | pm.y | pm.z | pm.w) != 0u;
     for (uint32_t g0 = 0; g0 < cnt; g0 += 8u) {
         uint64_t w[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) w[i] = words[a + g0 + (uint32_t)i];
 #pragma unroll
         for (int i = 0; i < 8; ++i)
-            if (g0 + (uint32_t)i < cnt) ripple_add(planes, p0 + g0 + (uint32_t)i, w[i], P);
+            if (g0 + (uint32_t)i < cnt && !(prune && pruned_at(pm, p0 + g0 + (uint32_t)i)))
+                ripple_add(planes, p0 + g0 + (uint32_t)i, w[i], P);
     }
 }
 
@@ -319,7 +325,34 @@ __device__ uint64_t* ewt_phase_buf;
 #endif
 
 // Misc LDS slots.
-enum { M_NDENSE = 1, M_ONEFULL = 4, M_NONZERO = 5, M_TMP = 8, M_X = 32, M_TOT = 40 };
+enum { M_NDENSE = 1, M_PSUM = 2, M_ONEFULL = 4, M_NONZERO = 5, M_DFULL = 6, M_TMP = 8, M_X = 32, M_TOT = 40, M_PR = 44 };
+
+// Presence group of tile-relative position rel is pruned (bit rel / GW of the
+// 128-bit mask; positions outside the tile are never pruned).
+__device__ __forceinline__ bool pruned_at(const uint4& pm, uint32_t rel) {
+    const uint32_t g = rel / (uint32_t)GW;
+    const uint32_t w = g < 32u ? pm.x : g < 64u ? pm.y : g < 96u ? pm.z : pm.w;
+    return g < 128u && ((w >> (g & 31u)) & 1u);
+}
+
+// Adds, for every presence group of the tile, the number of this wavefront's
+// inputs (lanes with valid set) that touch it into cnt[g] (LDS).
+__device__ __forceinline__ void count_presence(const uint4& pr, bool valid, uint32_t* cnt) {
+    const int lane = __lane_id();
+    const uint64_t lo = valid ? ((uint64_t)pr.y << 32 | pr.x) : 0ull;
+    const uint64_t hi = valid ? ((uint64_t)pr.w << 32 | pr.z) : 0ull;
+    if (__ballot(valid) == 0ull) return;
+    uint32_t cl = 0, ch = 0;   // lane g holds the counts of groups g and 64 + g
+#pragma unroll 8
+    for (int g = 0; g < 64; ++g) {
+        const uint32_t a = (uint32_t)__popcll(__ballot((lo >> g) & 1ull));
+        const uint32_t b = (NGROUPS > 64) ? (uint32_t)__popcll(__ballot((hi >> g) & 1ull)) : 0u;
+        cl = lane == g ? a : cl;
+        ch = lane == g ? b : ch;
+    }
+    if (cl) atomicAdd(&cnt[lane], cl);
+    if (NGROUPS > 64 && ch) atomicAdd(&cnt[64 + lane], ch);
+}
 
 // Window list entry (16 bytes, one per 64-word window):
 //   x, y  address of the window's first word; bits 16..31 of y hold flags:
@@ -406,29 +439,68 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     EWT_PHASE(0);
     for (int i = tid; i < P * TW; i += BLOCK) planes[i] = 0;
     for (int i = tid; i < TW + 8; i += BLOCK) diff[i] = 0;
+    uint32_t* gcnt = (uint32_t*)win;   // presence counts per group (the window list is not in use yet)
+    if (tid < NGROUPS) gcnt[tid] = 0;
     if (tid < 8) misc[tid] = 0;
+    if (tid < 4) misc[M_PR + tid] = 0;
     __syncthreads();
 
     // ---- classify / prune (RBMrg on EWAH, cases 1 and 2, per tile)
     const bool trivial = (T == 0) || (T > N);
     Seg seg;
     BitmapDev B0;
+    uint4 pr0 = make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t ngv = (nPos + (uint32_t)GW - 1u) / (uint32_t)GW;   // presence groups inside the tile
     if (!trivial) {
         for (uint32_t kb = 0; kb < N; kb += BLOCK) {
             uint32_t k = kb + (uint32_t)tid;
+            bool onefull = false, nonzero = false;
+            uint32_t np = 0;
             if (k < N) {
                 const BitmapDev B = gp(table)[gp(q.ids)[k]];
+                const uint4 pr = gp(B.pres)[t];
                 Seg s = locate(B, t, tS, tE, tiles);
-                if (s.onefull) atomicAdd(&misc[M_ONEFULL], 1u);
-                if (!s.zero) atomicAdd(&misc[M_NONZERO], 1u);
-                if (kb == 0) { seg = s; B0 = B; }
+                onefull = s.onefull;
+                nonzero = !s.zero;
+                np = (uint32_t)(__popc(pr.x) + __popc(pr.y) + __popc(pr.z) + __popc(pr.w));
+                if (kb == 0) { seg = s; B0 = B; pr0 = pr; }
+            }
+            // one LDS atomic per wavefront and counter
+            const uint32_t c1 = (uint32_t)__popcll(__ballot(onefull)), c2 = (uint32_t)__popcll(__ballot(nonzero));
+            const uint32_t c3 = (uint32_t)__popcll(__ballot(np == ngv && k < N));
+            const uint32_t c4 = wave_incl_scan(np);
+            if (lane == 63) {
+                if (c1) atomicAdd(&misc[M_ONEFULL], c1);
+                if (c2) atomicAdd(&misc[M_NONZERO], c2);
+                if (c3) atomicAdd(&misc[M_DFULL], c3);
+                if (c4) atomicAdd(&misc[M_PSUM], c4);
             }
         }
     }
     __syncthreads();
     EWT_PHASE(1);
-    const uint32_t mode = trivial ? (T == 0 ? 1u : 2u)
-                                  : (misc[M_ONEFULL] >= T ? 1u : (misc[M_NONZERO] < T ? 2u : 0u));
+    uint32_t mode = trivial ? (T == 0 ? 1u : 2u)
+                            : (misc[M_ONEFULL] >= T ? 1u : (misc[M_NONZERO] < T ? 2u : 0u));
+    // per-group bounds: counted only when fewer than T inputs touch every group and
+    // T is above 9/10 of the mean bound (else few groups, if any, fall below T)
+    uint4 pm = make_uint4(0u, 0u, 0u, 0u);
+    if (mode == 0 && misc[M_DFULL] < T && 10ull * T * ngv > 9ull * misc[M_PSUM]) {
+        for (uint32_t kb = 0; kb < N; kb += BLOCK) {
+            const uint32_t k = kb + (uint32_t)tid;
+            uint4 pr = pr0;
+            if (kb != 0 && k < N) pr = gp(gp(table)[gp(q.ids)[k]].pres)[t];
+            count_presence(pr, k < N, gcnt);
+        }
+        __syncthreads();
+        if (tid < NGROUPS) {
+            const uint64_t m = __ballot(gcnt[tid] < T && (uint32_t)tid < ngv);
+            if ((tid & 63) == 0) { misc[M_PR + 2 * (tid >> 6)] = (uint32_t)m; misc[M_PR + 2 * (tid >> 6) + 1] = (uint32_t)(m >> 32); }
+        }
+        __syncthreads();
+        pm = make_uint4(misc[M_PR], misc[M_PR + 1], misc[M_PR + 2], misc[M_PR + 3]);
+        if ((uint32_t)(__popc(pm.x) + __popc(pm.y) + __popc(pm.z) + __popc(pm.w)) == ngv) mode = 2u;
+    }
+    const bool prune = (pm.x | pm.y | pm.z | pm.w) != 0u;
 
     // ---- decode and count
     if (mode == 0) {
@@ -450,13 +522,13 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                         uint32_t j = atomicAdd(&misc[M_NDENSE], 1u);
                         dense[j] = wp + s.a_lit;
                     } else if (s.cnt <= litwalk_max) {
-                        lit_lane(gp(wp), s.a_lit, s.cnt, s.la - tS, planes, P);
+                        lit_lane(gp(wp), s.a_lit, s.cnt, s.la - tS, planes, P, pm);
                     } else {
                         nlw = (s.cnt + 63u) / 64u;
                     }
                 }
                 if (s.be > s.bs) {
-                    if (s.be - s.bs <= walk_max) walk_lane(gp(wp), s.bs, s.be, s.y0, tS, tE, planes, diff, P);
+                    if (s.be - s.bs <= walk_max) walk_lane(gp(wp), s.bs, s.be, s.y0, tS, tE, planes, diff, P, pm);
                     else nww = (s.be - 1u) / 64u - s.bs / 64u + 1u;
                 }
             }
@@ -519,6 +591,11 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                             }
                         }
                     }
+                    // words in pruned groups add nothing
+                    if (prune) {
+#pragma unroll
+                        for (int g = 0; g < WIN_BATCH; ++g) lit[g] &= ~__ballot(pruned_at(pm, r[g] - tS));
+                    }
                     // dirty words in range add at their tile-relative position
                     uint32_t act = 0;   // bit g: window g still carries somewhere
 #pragma unroll
@@ -560,7 +637,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             EWT_PHASE(3);
             // dense rows: Harley-Seal carry-save-adder tree, one lane per word position
             const uint32_t n_dense = misc[M_NDENSE];
-            if (n_dense && (uint32_t)tid < nPos) {
+            if (n_dense && (uint32_t)tid < nPos && !(prune && pruned_at(pm, (uint32_t)tid))) {
                 uint64_t R[MAXP];
 #pragma unroll
                 for (int p = 0; p < MAXP; ++p) R[p] = 0;
