@@ -54,7 +54,7 @@ struct Ctx {                       // per-stream query state
     uint32_t* h_ids = nullptr;     // pinned staging
     TileState* d_state = nullptr;
     size_t state_cap = 0;
-    uint32_t* d_ticket = nullptr;
+    uint32_t* d_ticket = nullptr;  // tile order of the single-query kernel
     uint32_t epoch = 0;
     hipEvent_t ev = nullptr;       // staging buffer free once this completes
 };
@@ -457,6 +457,7 @@ ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t 
     q.out = out_words_dev;
     q.out_n = out_n_words_dev;
     q.state = c->d_state;
+    q.stage = nullptr;             // the single-query kernel writes its output in place
     q.cap = out_cap;
     q.N = n;
     q.T = T;
@@ -494,6 +495,9 @@ struct ewah_batch {
     uint32_t* d_qtile = nullptr;
     uint32_t* d_ids = nullptr;
     TileState* d_state = nullptr;
+    uint64_t* d_stage = nullptr;   // STAGE_WORDS per tile of every query
+    uint32_t* d_tq = nullptr;      // query of every (query, tile) item
+    uint32_t total = 0;            // (query, tile) items
     uint32_t* d_work = nullptr;    // work counter, epoch
     uint32_t* d_codes = nullptr;   // variant codes for ewah_batch_select
     std::vector<uint32_t> h_codes; // their host copy (upload only on change)
@@ -516,8 +520,8 @@ ewah_status batch_build_graph(ewah_batch* b) {
     if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = launch_bump(b->d_work + 1, b->cap_stream);
-    hipError_t e2 = launch_batch(b->d_qs, b->d_qtile, b->nq, g.d_table, b->d_work, b->d_work + 1, g.d_err, b->grid,
-                                 b->smem, b->cap_stream);
+    hipError_t e2 = launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1,
+                                 g.d_err, b->grid, b->smem, b->cap_stream);
     hipError_t e3 = hipStreamEndCapture(b->cap_stream, &b->graph);
     HIPCHK(e1);
     HIPCHK(e2);
@@ -572,6 +576,16 @@ ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, con
     HIPCHK(hipMemcpy(b->d_ids, ids.data(), ids.size() * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMalloc(&b->d_state, (size_t)qtile[nq] * sizeof(TileState)));
     HIPCHK(hipMemset(b->d_state, 0, (size_t)qtile[nq] * sizeof(TileState)));
+    if (hipMalloc(&b->d_stage, (size_t)qtile[nq] * STAGE_WORDS * sizeof(uint64_t)) != hipSuccess)
+        return fail(EWAH_ENOMEM, "staging area of " + std::to_string((size_t)qtile[nq] * STAGE_WORDS * 8) + " bytes");
+    {
+        std::vector<uint32_t> tq(qtile[nq]);
+        for (uint32_t i = 0; i < nq; ++i)
+            for (uint32_t j = qtile[i]; j < qtile[i + 1]; ++j) tq[j] = i;
+        HIPCHK(hipMalloc(&b->d_tq, std::max<size_t>(tq.size(), 1) * 4));
+        if (!tq.empty()) HIPCHK(hipMemcpy(b->d_tq, tq.data(), tq.size() * 4, hipMemcpyHostToDevice));
+        b->total = qtile[nq];
+    }
     HIPCHK(hipMalloc(&b->d_qtile, (nq + 1) * 4));
     HIPCHK(hipMemcpy(b->d_qtile, qtile.data(), (nq + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMalloc(&b->d_work, 256));
@@ -585,6 +599,7 @@ ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, con
         d.out = q[i].out_words_dev;
         d.out_n = q[i].out_n_words_dev;
         d.state = b->d_state + qtile[i];
+        d.stage = b->d_stage + (size_t)qtile[i] * STAGE_WORDS;
         d.cap = q[i].out_cap;
         d.N = q[i].n;
         d.T = q[i].T;
@@ -611,7 +626,8 @@ ewah_status ewah_batch_run(ewah_batch* b, void* hip_stream) {
         HIPCHK(hipGraphLaunch(b->exec, s));
     } else {
         HIPCHK(launch_bump(b->d_work + 1, s));
-        HIPCHK(launch_batch(b->d_qs, b->d_qtile, b->nq, g.d_table, b->d_work, b->d_work + 1, g.d_err, b->grid, b->smem, s));
+        HIPCHK(launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1, g.d_err,
+                            b->grid, b->smem, s));
     }
     return EWAH_OK;
 }
@@ -641,6 +657,8 @@ void ewah_batch_free(ewah_batch* b) {
     (void)hipFree(b->d_qtile);
     (void)hipFree(b->d_ids);
     (void)hipFree(b->d_state);
+    (void)hipFree(b->d_stage);
+    (void)hipFree(b->d_tq);
     (void)hipFree(b->d_work);
     (void)hipFree(b->d_codes);
     delete b;

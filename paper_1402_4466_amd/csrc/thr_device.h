@@ -36,10 +36,13 @@
 //   5. compare: per word position, the bit-sliced count is compared with
 //      T' = T - (number of one-fills at that position) (greater-than-or-equal,
 //      cf. the comparison step of BSTM, Section 5.3.1);
-//   6. encode: canonical EWAH by scan-and-compact; the tile's run structure is
-//      summarised in an associative aggregate and the exclusive prefix over
-//      earlier tiles is obtained by decoupled look-back, so markers spanning
-//      tiles are closed by the tile that holds the next marker.
+//   6. encode: canonical EWAH by scan-and-compact.  Each tile writes its words
+//      at local output indices to a staging area and publishes its run
+//      structure as an associative aggregate; no tile waits for another.  A
+//      placement pass then scans the aggregates of each query (exclusive prefix
+//      per tile), moves every tile's words to their final index and writes the
+//      markers of runs that span tiles (closed by the tile that holds the next
+//      marker).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -89,15 +92,18 @@ struct Agg {
 // they wrap.
 struct TileState {
     uint64_t local[3];    // aggregate of this tile alone
-    uint64_t incl[3];     // aggregate of tiles 0..t
-    uint64_t pad[2];
+    uint64_t incl[3];     // single queries: aggregate of tiles 0..t (look-back); batches: of tiles
+                          // 0..t-1, written by the placement scan
+    uint64_t head[2];     // first two heads of the tile: position | local output index << 32;
+                          // bits 16..17 of head[1]: number of heads, at most 2
 };
 
-struct QueryDev {         // 64 bytes
+struct QueryDev {         // 72 bytes
     const uint32_t* ids;  // N bitmap slots
     uint64_t* out;        // canonical EWAH output (device)
     uint64_t* out_n;      // output length (device)
     TileState* state;     // tiles entries
+    uint64_t* stage;      // tiles * STAGE_WORDS words: each tile's output before placement
     uint64_t cap;         // output capacity in words
     uint32_t N, T, U, tiles;
     uint32_t tail_bits;   // n_bits % 64
@@ -124,6 +130,7 @@ __host__ __device__ inline int planes_for(uint32_t n) {
 }
 
 constexpr int WCAP = 2 * BLOCK;   // cooperative windows listed in LDS per round
+constexpr int STAGE_WORDS = TW + 8;   // staged output words per tile (at most TW + 1 are used)
 
 // LDS bytes needed by the tile routine for a query with N inputs.
 __host__ __device__ inline size_t tile_smem_bytes(uint32_t N) {
@@ -139,8 +146,9 @@ __host__ __device__ inline size_t tile_smem_bytes(uint32_t N) {
 // Host-side launchers (defined with the kernels).
 hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* ticket, uint32_t epoch, uint32_t* err,
                         hipStream_t s);
-hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, uint32_t nq, const BitmapDev* table, uint32_t* work,
-                        const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid, size_t smem, hipStream_t s);
+hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_t* tq, uint32_t nq, uint32_t total,
+                        const BitmapDev* table, uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid,
+                        size_t smem, hipStream_t s);
 hipError_t launch_bump(uint32_t* epoch, hipStream_t s);
 hipError_t launch_zero_len(uint64_t* out_n, hipStream_t s);
 hipError_t set_smem_limits(size_t max_bytes);

@@ -417,6 +417,10 @@ __device__ __forceinline__ void issue_batch(const uint4* win, uint32_t w0, uint3
     }
 }
 
+// STAGED: the tile writes its words to the staging area and publishes its
+// aggregate (a placement pass finishes the output); otherwise it finds the prefix
+// over earlier tiles by look-back and writes its words in place.
+template <bool STAGED>
 __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ table, uint32_t t,
                              uint32_t epoch, unsigned char* smem, uint32_t* err, uint32_t dbg_slot) {
     (void)dbg_slot;   // timestamp slot of debug builds
@@ -730,89 +734,263 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     if (hl) { hpos[ex_head] = (uint16_t)tid; hout[ex_head] = (uint16_t)ex_emit; }
     __syncthreads();
 
-    if (wave == 0) {
-        // local aggregate of this tile (every lane of wave 0 computes it)
-        Agg A;
-        A.n = n_local;
-        uint32_t bits = (uint32_t)clsA[0] | ((uint32_t)clsA[nPos - 1] << 2);
-        if (nheads) {
-            uint32_t lh = hpos[nheads - 1];
-            A.lh_pos = tS + lh;
-            A.lh_out = hout[nheads - 1];
-            bits |= (1u << 4) | ((clsA[lh] == 1u ? 1u : 0u) << 5);
-        } else {
-            A.lh_pos = 0; A.lh_out = 0;
+    if constexpr (STAGED) {
+        // ---- staged output: literals at their local output index, markers of the runs
+        // that end inside the tile; the placement pass moves them to their final index
+        // and writes the markers of runs that continue across tiles
+        EWT_GLOBAL uint64_t* stage = gp(q.stage) + (size_t)t * STAGE_WORDS;
+        if (act) {
+            if (cls == 2u) stage[ex_emit + hl] = o;
+            if (hl && ex_head + 1u < nheads) {
+                const uint32_t nh = hpos[ex_head + 1];
+                const uint32_t K = hout[ex_head + 1] - ex_emit - 1u;
+                const uint32_t L = (nh - (uint32_t)tid) - K;
+                stage[ex_emit] = (cls == 1u ? 1ull : 0ull) | ((uint64_t)L << 1) | ((uint64_t)K << 33);
+            }
         }
-        A.bits = bits;
-        EWT_GLOBAL TileState* st = gp(q.state);
-        Agg X;
-        X.n = 0; X.lh_pos = 0; X.lh_out = 0; X.bits = 3u << 2;
-        Agg I = A;
-        if (t > 0) {
-            if (lane == 0) agg_publish(st[t].local, A, epoch);
-            X = lookback(st, (int)t, epoch, err);
-            I = agg_combine(X, A, tS);
+        if (tid == 0) {
+            Agg A;
+            A.n = n_local;
+            uint32_t bits = (uint32_t)clsA[0] | ((uint32_t)clsA[nPos - 1] << 2);
+            if (nheads) {
+                const uint32_t lh = hpos[nheads - 1];
+                A.lh_pos = tS + lh;
+                A.lh_out = hout[nheads - 1];
+                bits |= (1u << 4) | ((clsA[lh] == 1u ? 1u : 0u) << 5);
+            } else {
+                A.lh_pos = 0; A.lh_out = 0;
+            }
+            A.bits = bits;
+            EWT_GLOBAL TileState* st = gp(q.state);
+            const uint64_t h0 = nheads > 0 ? ((uint64_t)hpos[0] | ((uint64_t)hout[0] << 32)) : 0ull;
+            const uint64_t h1 = nheads > 1 ? ((uint64_t)hpos[1] | ((uint64_t)hout[1] << 32)) : 0ull;
+            st[t].head[0] = h0;
+            st[t].head[1] = h1 | ((uint64_t)min(nheads, 2u) << 16);
+            agg_publish(st[t].local, A, epoch);
         }
-        if (lane == 0) {
-            agg_publish(st[t].incl, I, epoch);
-            misc[M_X + 0] = X.n; misc[M_X + 1] = X.lh_pos; misc[M_X + 2] = X.lh_out; misc[M_X + 3] = X.bits;
-            misc[M_TOT] = I.n;
+        EWT_PHASE(6);
+        __syncthreads();
+    } else {
+        // ---- prefix over earlier tiles by look-back, words written in place
+        if (wave == 0) {
+            // local aggregate of this tile (every lane of wave 0 computes it)
+            Agg A;
+            A.n = n_local;
+            uint32_t bits = (uint32_t)clsA[0] | ((uint32_t)clsA[nPos - 1] << 2);
+            if (nheads) {
+                uint32_t lh = hpos[nheads - 1];
+                A.lh_pos = tS + lh;
+                A.lh_out = hout[nheads - 1];
+                bits |= (1u << 4) | ((clsA[lh] == 1u ? 1u : 0u) << 5);
+            } else {
+                A.lh_pos = 0; A.lh_out = 0;
+            }
+            A.bits = bits;
+            EWT_GLOBAL TileState* st = gp(q.state);
+            Agg X;
+            X.n = 0; X.lh_pos = 0; X.lh_out = 0; X.bits = 3u << 2;
+            Agg I = A;
+            if (t > 0) {
+                if (lane == 0) agg_publish(st[t].local, A, epoch);
+                X = lookback(st, (int)t, epoch, err);
+                I = agg_combine(X, A, tS);
+            }
+            if (lane == 0) {
+                agg_publish(st[t].incl, I, epoch);
+                misc[M_X + 0] = X.n; misc[M_X + 1] = X.lh_pos; misc[M_X + 2] = X.lh_out; misc[M_X + 3] = X.bits;
+                misc[M_TOT] = I.n;
+            }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    EWT_PHASE(6);
-    const uint32_t Xn = misc[M_X + 0], Xlh_pos = misc[M_X + 1], Xlh_out = misc[M_X + 2], Xbits = misc[M_X + 3];
-    const uint32_t total = misc[M_TOT];
-    const uint32_t c0 = clsA[0];
-    const uint32_t merge = (t > 0 && c0 != 2u && ((Xbits >> 2) & 3u) == c0) ? 1u : 0u;
+        EWT_PHASE(6);
+        const uint32_t Xn = misc[M_X + 0], Xlh_pos = misc[M_X + 1], Xlh_out = misc[M_X + 2], Xbits = misc[M_X + 3];
+        const uint32_t total = misc[M_TOT];
+        const uint32_t c0 = clsA[0];
+        const uint32_t merge = (t > 0 && c0 != 2u && ((Xbits >> 2) & 3u) == c0) ? 1u : 0u;
+        const uint64_t cap = q.cap;
+        EWT_GLOBAL uint64_t* out = gp(q.out);
+        auto out_of = [&](uint32_t i, uint32_t local_ex) -> uint32_t { return Xn + local_ex - (i > 0 ? merge : 0u); };
+
+        if (act) {
+            const uint32_t my_out = out_of((uint32_t)tid, ex_emit);
+            if (cls == 2u) {
+                uint32_t idx = my_out + hl;
+                if (idx < cap) out[idx] = o;
+            }
+            if (hl && !(tid == 0 && merge)) {
+                const uint32_t r = ex_head;
+                if (r + 1u < nheads) {
+                    uint32_t nh = hpos[r + 1];
+                    uint32_t nh_out = out_of(nh, hout[r + 1]);
+                    uint32_t K = nh_out - my_out - 1u;
+                    uint32_t L = (nh - (uint32_t)tid) - K;
+                    uint64_t f = cls == 1u ? 1ull : 0ull;
+                    if (my_out < cap) out[my_out] = f | ((uint64_t)L << 1) | ((uint64_t)K << 33);
+                }
+                // the first actual head of the tile closes the group left open by earlier tiles
+                if (t > 0 && r == merge) {
+                    uint32_t K = my_out - Xlh_out - 1u;
+                    uint32_t L = (tS + (uint32_t)tid - Xlh_pos) - K;
+                    uint64_t f = (Xbits >> 5) & 1u;
+                    if (Xlh_out < cap) out[Xlh_out] = f | ((uint64_t)L << 1) | ((uint64_t)K << 33);
+                }
+            }
+        }
+        if (t == tiles - 1 && tid == 0) {
+            uint32_t lpos, lout;
+            uint64_t lf;
+            if (nheads > merge) {
+                uint32_t h = hpos[nheads - 1];
+                lpos = tS + h;
+                lout = out_of(h, hout[nheads - 1]);
+                lf = clsA[h] == 1u ? 1ull : 0ull;
+            } else {
+                lpos = Xlh_pos; lout = Xlh_out; lf = (Xbits >> 5) & 1u;
+            }
+            uint32_t K = total - lout - 1u;
+            uint32_t L = (U - lpos) - K;
+            if (lout < cap) out[lout] = lf | ((uint64_t)L << 1) | ((uint64_t)K << 33);
+            *gp(q.out_n) = total;
+        }
+        __syncthreads();
+    }
+    EWT_PHASE(7);
+}
+
+// ------------------------------------------------------------ output placement
+
+// Exclusive prefix of the tile aggregates of one query (one workgroup of
+// SCAN_THREADS threads, tiles in chunks): X_t = A_0 + ... + A_(t-1), written into
+// the tile's state for the placement kernel.
+constexpr int SCAN_THREADS = 1024;
+
+__device__ void scan_query(const QueryDev& q, uint32_t epoch, uint32_t* err) {
+    __shared__ uint32_t part[SCAN_THREADS / 64][5];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    EWT_GLOBAL TileState* st = gp(q.state);
+    Agg carry;
+    carry.n = 0; carry.lh_pos = 0; carry.lh_out = 0; carry.bits = 0;
+    bool carry_empty = true;
+    for (uint32_t base = 0; base < q.tiles; base += SCAN_THREADS) {
+        const uint32_t i = base + (uint32_t)tid;
+        const bool in = i < q.tiles;
+        Agg v;
+        v.n = 0; v.lh_pos = 0; v.lh_out = 0; v.bits = 0;
+        bool valid = in;
+        if (valid && !agg_fetch(st[i].local, epoch, v)) {
+            atomicOr(err, 4u);
+            valid = false;
+        }
+        // inclusive scan inside the wavefront: lane l - d holds the earlier tiles
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            Agg o;
+            o.n = __shfl_up(v.n, d, 64);
+            o.lh_pos = __shfl_up(v.lh_pos, d, 64);
+            o.lh_out = __shfl_up(v.lh_out, d, 64);
+            o.bits = __shfl_up(v.bits, d, 64);
+            const bool ov = __shfl_up((int)valid, d, 64) != 0 && lane >= d;
+            if (ov) {
+                if (valid) v = agg_combine(o, v, (i - (uint32_t)d + 1u) * (uint32_t)TW);
+                else { v = o; valid = true; }
+            }
+        }
+        if (lane == 63) {
+            part[wave][0] = v.n; part[wave][1] = v.lh_pos; part[wave][2] = v.lh_out; part[wave][3] = v.bits;
+            part[wave][4] = valid ? 1u : 0u;
+        }
+        __syncthreads();
+        // earlier wavefronts of the chunk, then the carry of earlier chunks
+        Agg pre;
+        pre.n = 0; pre.lh_pos = 0; pre.lh_out = 0; pre.bits = 0;
+        bool pre_valid = false;
+        for (int w = 0; w < wave; ++w) {
+            if (!part[w][4]) continue;
+            Agg b;
+            b.n = part[w][0]; b.lh_pos = part[w][1]; b.lh_out = part[w][2]; b.bits = part[w][3];
+            if (pre_valid) pre = agg_combine(pre, b, (base + (uint32_t)w * 64u) * (uint32_t)TW);
+            else { pre = b; pre_valid = true; }
+        }
+        if (!carry_empty) {
+            pre = pre_valid ? agg_combine(carry, pre, base * (uint32_t)TW) : carry;
+            pre_valid = true;
+        }
+        // inclusive prefix of tile i, and the exclusive one (inclusive of tile i - 1)
+        Agg inc = v;
+        if (pre_valid && valid) inc = agg_combine(pre, v, (base + (uint32_t)wave * 64u) * (uint32_t)TW);
+        Agg ex;
+        ex.n = __shfl_up(inc.n, 1, 64);
+        ex.lh_pos = __shfl_up(inc.lh_pos, 1, 64);
+        ex.lh_out = __shfl_up(inc.lh_out, 1, 64);
+        ex.bits = __shfl_up(inc.bits, 1, 64);
+        if (lane == 0) ex = pre;
+        if (in && i > 0) agg_publish(st[i].incl, ex, epoch);
+        // carry: inclusive prefix of the chunk's last valid tile
+        const uint32_t last = min(q.tiles - base, (uint32_t)SCAN_THREADS) - 1u;
+        __syncthreads();
+        if ((uint32_t)tid == last) {
+            part[0][0] = inc.n; part[0][1] = inc.lh_pos; part[0][2] = inc.lh_out; part[0][3] = inc.bits;
+        }
+        __syncthreads();
+        carry.n = part[0][0]; carry.lh_pos = part[0][1]; carry.lh_out = part[0][2]; carry.bits = part[0][3];
+        carry_empty = false;
+        __syncthreads();
+    }
+}
+
+// Moves the staged words of tile t to their place and writes the markers of runs
+// crossing into the tile (one wavefront per tile).
+__device__ void place_tile(const QueryDev& q, uint32_t t, uint32_t epoch, uint32_t* err) {
+    const int lane = __lane_id();
+    EWT_GLOBAL TileState* st = gp(q.state);
+    Agg A, X;
+    if (!agg_fetch(st[t].local, epoch, A)) { if (lane == 0) atomicOr(err, 8u); return; }
+    X.n = 0; X.lh_pos = 0; X.lh_out = 0; X.bits = 3u << 2;
+    if (t > 0 && !agg_fetch(st[t].incl, epoch, X)) { if (lane == 0) atomicOr(err, 8u); return; }
+    const uint64_t h0 = st[t].head[0], h1w = st[t].head[1];
+    const uint32_t nheads = (uint32_t)(h1w >> 16) & 3u;
+    const uint32_t tS = t * (uint32_t)TW;
+    const uint32_t c0 = A.bits & 3u;
+    const uint32_t merge = (t > 0 && c0 != 2u && ((X.bits >> 2) & 3u) == c0) ? 1u : 0u;
     const uint64_t cap = q.cap;
     EWT_GLOBAL uint64_t* out = gp(q.out);
-    auto out_of = [&](uint32_t i, uint32_t local_ex) -> uint32_t { return Xn + local_ex - (i > 0 ? merge : 0u); };
-
-    if (act) {
-        const uint32_t my_out = out_of((uint32_t)tid, ex_emit);
-        if (cls == 2u) {
-            uint32_t idx = my_out + hl;
-            if (idx < cap) out[idx] = o;
+    const EWT_GLOBAL uint64_t* stage = gp(q.stage) + (size_t)t * STAGE_WORDS;
+    // the marker slot of the tile's last head stays unstaged (its run continues past
+    // the tile): a later tile or the last one writes it
+    const uint32_t open = ((A.bits >> 4) & 1u) ? A.lh_out : 0xFFFFFFFFu;
+    for (uint32_t e = merge + (uint32_t)lane; e < A.n; e += 64u) {
+        const uint32_t idx = X.n + e - merge;
+        if (e != open && idx < cap) out[idx] = stage[e];
+    }
+    if (lane == 0) {
+        // the first head of the tile that starts a run closes the run left open before it
+        if (t > 0 && nheads > merge) {
+            const uint64_t h = merge ? h1w : h0;
+            const uint32_t hp = (uint32_t)h & 0xFFFFu, ho = (uint32_t)(h >> 32);
+            const uint32_t my_out = X.n + ho - merge;
+            const uint32_t K = my_out - X.lh_out - 1u;
+            const uint32_t L = (tS + hp - X.lh_pos) - K;
+            if (X.lh_out < cap) out[X.lh_out] = ((X.bits >> 5) & 1u) | ((uint64_t)L << 1) | ((uint64_t)K << 33);
         }
-        if (hl && !(tid == 0 && merge)) {
-            const uint32_t r = ex_head;
-            if (r + 1u < nheads) {
-                uint32_t nh = hpos[r + 1];
-                uint32_t nh_out = out_of(nh, hout[r + 1]);
-                uint32_t K = nh_out - my_out - 1u;
-                uint32_t L = (nh - (uint32_t)tid) - K;
-                uint64_t f = cls == 1u ? 1ull : 0ull;
-                if (my_out < cap) out[my_out] = f | ((uint64_t)L << 1) | ((uint64_t)K << 33);
+        if (t == q.tiles - 1) {   // the last tile closes the last run
+            const Agg I = t > 0 ? agg_combine(X, A, tS) : A;
+            uint32_t lpos, lout;
+            uint64_t lf;
+            if (nheads > merge) {
+                lpos = A.lh_pos;
+                lout = X.n + A.lh_out - (A.lh_pos > tS ? merge : 0u);
+                lf = (A.bits >> 5) & 1u;
+            } else {
+                lpos = X.lh_pos; lout = X.lh_out; lf = (X.bits >> 5) & 1u;
             }
-            // the first actual head of the tile closes the group left open by earlier tiles
-            if (t > 0 && r == merge) {
-                uint32_t K = my_out - Xlh_out - 1u;
-                uint32_t L = (tS + (uint32_t)tid - Xlh_pos) - K;
-                uint64_t f = (Xbits >> 5) & 1u;
-                if (Xlh_out < cap) out[Xlh_out] = f | ((uint64_t)L << 1) | ((uint64_t)K << 33);
-            }
+            const uint32_t K = I.n - lout - 1u;
+            const uint32_t L = (q.U - lpos) - K;
+            if (lout < cap) out[lout] = lf | ((uint64_t)L << 1) | ((uint64_t)K << 33);
+            *gp(q.out_n) = I.n;
         }
     }
-    if (t == tiles - 1 && tid == 0) {
-        uint32_t lpos, lout;
-        uint64_t lf;
-        if (nheads > merge) {
-            uint32_t h = hpos[nheads - 1];
-            lpos = tS + h;
-            lout = out_of(h, hout[nheads - 1]);
-            lf = clsA[h] == 1u ? 1ull : 0ull;
-        } else {
-            lpos = Xlh_pos; lout = Xlh_out; lf = (Xbits >> 5) & 1u;
-        }
-        uint32_t K = total - lout - 1u;
-        uint32_t L = (U - lpos) - K;
-        if (lout < cap) out[lout] = lf | ((uint64_t)L << 1) | ((uint64_t)K << 33);
-        *gp(q.out_n) = total;
-    }
-    __syncthreads();
-    EWT_PHASE(7);
 }
 
 // ----------------------------------------------------------------- kernels
@@ -831,7 +1009,7 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_kernel(QueryDev q, const B
         s_t = t;
     }
     __syncthreads();
-    process_tile(q, table, s_t, epoch, smem, err, s_t);
+    process_tile<false>(q, table, s_t, epoch, smem, err, s_t);
 }
 
 // Many queries in one persistent launch: workgroups take (query, tile) items
@@ -863,8 +1041,24 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __r
         const uint32_t it = s_item, qi = s_q;
         if (it >= total) break;
         QueryDev q = qs[qi];
-        process_tile(q, table, it - qtile[qi], epoch, smem, err, it);
+        process_tile<true>(q, table, it - qtile[qi], epoch, smem, err, it);
     }
+}
+
+// Output placement of a batch: one workgroup per query for the prefixes, then one
+// wavefront per (query, tile); tq[i] = query of item i.
+__global__ __launch_bounds__(SCAN_THREADS) void scan_batch_kernel(const QueryDev* __restrict__ qs, const uint32_t* epoch_ptr,
+                                                                   uint32_t* err) {
+    scan_query(qs[blockIdx.x], *epoch_ptr, err);
+}
+__global__ __launch_bounds__(256) void place_batch_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
+                                                           const uint32_t* __restrict__ tq, uint32_t total,
+                                                           const uint32_t* epoch_ptr, uint32_t* err) {
+    const uint32_t it = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (it >= total) return;
+    const uint32_t qi = tq[it];
+    const QueryDev q = qs[qi];
+    place_tile(q, it - qtile[qi], *epoch_ptr, err);
 }
 
 // Next launch tag of a batch; tag 0 (the value of cleared states) is skipped.
@@ -903,9 +1097,12 @@ hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* tic
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, uint32_t nq, const BitmapDev* table, uint32_t* work,
-                        const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid, size_t smem, hipStream_t s) {
+hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_t* tq, uint32_t nq, uint32_t total,
+                        const BitmapDev* table, uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid,
+                        size_t smem, hipStream_t s) {
     hipLaunchKernelGGL(thr_batch_kernel, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, nq, table, work, epoch_ptr, err);
+    hipLaunchKernelGGL(scan_batch_kernel, dim3(nq), dim3(SCAN_THREADS), 0, s, qs, epoch_ptr, err);
+    hipLaunchKernelGGL(place_batch_kernel, dim3((total + 3) / 4), dim3(256), 0, s, qs, qtile, tq, total, epoch_ptr, err);
     return hipGetLastError();
 }
 
