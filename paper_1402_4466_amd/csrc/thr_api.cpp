@@ -86,7 +86,7 @@ ewah_status ensure_ready() {
 struct Built {
     std::vector<uint4> loc;    // per tile boundary: covering marker index, its run start, the marker word
     std::vector<uint4> desc;   // per CHUNK words: marker mask (lo, hi), position of the chunk's first word
-    std::vector<uint4> pres;   // per tile: groups of GW words holding a dirty word or a one-fill
+    std::vector<uint4> pres;   // per tile PV records: groups of GW words holding a dirty word or a one-fill
     ewah_stats st{};
 };
 
@@ -174,14 +174,14 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
     }
     if (u != U) return fail(EWAH_EFORMAT, "stream covers " + std::to_string(u) + " words, expected " + std::to_string(U));
     if (tiles) b.loc[tiles] = make_uint4((uint32_t)nw, (uint32_t)U, 0, 0);
-    b.pres.assign(tiles, make_uint4(0, 0, 0, 0));
+    b.pres.assign(tiles * PV, make_uint4(0, 0, 0, 0));
     for (uint64_t t = 0; t < tiles; ++t) {
-        uint32_t q[4] = {0, 0, 0, 0};
-        for (int k = 0; k < NGROUPS / 32; ++k) {
+        uint32_t q[4 * PV] = {};
+        for (int k = 0; k < PMW; ++k) {
             const uint64_t g0 = t * NGROUPS + 32 * (uint64_t)k;   // 32-aligned: within one 64-bit word
             q[k] = (uint32_t)(gbits[g0 / 64] >> (g0 % 64));
         }
-        b.pres[t] = make_uint4(q[0], q[1], q[2], q[3]);
+        for (int v = 0; v < PV; ++v) b.pres[t * PV + v] = make_uint4(q[4 * v], q[4 * v + 1], q[4 * v + 2], q[4 * v + 3]);
     }
     st.index_bytes = (b.loc.size() + b.desc.size() + b.pres.size()) * sizeof(uint4);
     return EWAH_OK;

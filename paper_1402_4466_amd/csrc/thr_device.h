@@ -14,7 +14,7 @@
 //      that can hold a one in the tile are counted; the three cases of RBMrg on
 //      EWAH (Section 6.4) at tile granularity: >= T full one-fills -> all ones,
 //      fewer than T non-empty inputs -> all zeros, else count.  The second case
-//      is also applied per group of 8 words: the number of inputs holding a
+//      is also applied per group of GW words: the number of inputs holding a
 //      dirty word or a one-fill in the group bounds every row count there, so
 //      groups whose bound is below T are all zeros and nothing is added there
 //      (registration stores which groups each input touches);
@@ -55,9 +55,14 @@ namespace ewt {
 constexpr int TW = EWT_TILE_WORDS;    // tile width in uncompressed 64-bit words (= locator granularity)
 constexpr int BLOCK = EWT_TILE_WORDS; // threads per workgroup (one per word position of a tile)
 constexpr int NWAVES = BLOCK / 64;
-constexpr int GW = 8;                 // words per presence group (upper bounds on row counts)
-constexpr int NGROUPS = TW / GW;      // presence groups per tile (at most 128: one uint4 per tile)
-static_assert(NGROUPS <= 128 && NGROUPS % 64 == 0, "presence groups per tile");
+#ifndef EWT_GROUP_WORDS
+#define EWT_GROUP_WORDS 4         // words per presence group (host and device must agree)
+#endif
+constexpr int GW = EWT_GROUP_WORDS;   // words per presence group (upper bounds on row counts)
+constexpr int NGROUPS = TW / GW;      // presence groups per tile
+constexpr int PMW = NGROUPS / 32;     // 32-bit words of a tile's group mask
+constexpr int PV = (NGROUPS + 127) / 128;   // 16-byte presence records per tile and bitmap
+static_assert(NGROUPS >= 64 && NGROUPS <= 256 && NGROUPS % 64 == 0 && TW % GW == 0, "presence groups per tile");
 constexpr int CHUNK = 64;         // compressed words per skip-index entry (one wavefront)
 constexpr int MAXP = 12;          // bit planes: inputs per query < 2^12 (LDS budget)
 constexpr uint32_t MAXN = (1u << MAXP) - 1;
@@ -72,8 +77,9 @@ struct BitmapDev {
                              // uncompressed position where word 64c's coverage starts, 0}
     uint32_t n_words;
     uint32_t U;              // uncompressed words
-    const uint4* pres;       // per tile: bit g (of 128) set iff words [8g, 8g + 8) of the tile hold a
-                             // dirty word or a one-fill (the input can contribute to those rows)
+    const uint4* pres;       // per tile PV records: bit g (of NGROUPS) set iff words [GW g, GW g + GW)
+                             // of the tile hold a dirty word or a one-fill (the input can contribute
+                             // to those rows)
 };
 
 // Associative run-structure aggregate of a range of output words (see encode step).

@@ -160,12 +160,19 @@ __device__ __forceinline__ Seg locate(const BitmapDev& B, uint32_t t, uint32_t t
 // starts at y0) and adds whatever falls inside [tS, tE).  Words are read eight
 // at a time; streams are padded so reads up to CHUNK words past the end stay
 // inside the allocation.
-__device__ __forceinline__ bool pruned_at(const uint4& pm, uint32_t rel);
+// Groups of a tile whose count bound is below T: bit g of the NGROUPS-bit mask
+// in LDS (PMW words at w), read only where some group is pruned.
+struct PMask {
+    const uint32_t* w;
+    bool on;
+    __device__ bool any() const { return on; }
+};
+__device__ __forceinline__ bool pruned_at(const PMask& pm, uint32_t rel);
 
 __device__ __forceinline__ void walk_lane(const EWT_GLOBAL uint64_t* words, uint32_t bs, uint32_t be, uint32_t y0,
                                           uint32_t tS, uint32_t tE, uint64_t* planes, int32_t* diff, int P,
-                                          const uint4& pm) {
-    const bool prune = (pm.x | pm.y | pm.z | pm.w) != 0u;
+                                          const PMask& pm) {
+    const bool prune = pm.any();
     uint32_t nm = bs;    // index of the next marker
     uint32_t u = y0;     // run start of the next marker
     uint32_t lb = 0;     // the dirty word at index j sits at position lb + j (mod 2^32)
@@ -199,8 +206,8 @@ __device__ __forceinline__ void walk_lane(const EWT_GLOBAL uint64_t* words, uint
 // One lane adds cnt consecutive dirty words starting at compressed index a,
 // the first at tile-relative position p0.
 __device__ __forceinline__ void lit_lane(const EWT_GLOBAL uint64_t* words, uint32_t a, uint32_t cnt, uint32_t p0,
-                                         uint64_t* planes, int P, const uint4& pm) {
-    const bool prune = (pm.x | pm.y | pm.z | pm.w) != 0u;
+                                         uint64_t* planes, int P, const PMask& pm) {
+    const bool prune = pm.any();
     for (uint32_t g0 = 0; g0 < cnt; g0 += 8u) {
         uint64_t w[8];
 #pragma unroll
@@ -326,32 +333,33 @@ __device__ uint64_t* ewt_phase_buf;
 
 // Misc LDS slots.
 enum { M_NDENSE = 1, M_PSUM = 2, M_ONEFULL = 4, M_NONZERO = 5, M_DFULL = 6, M_TMP = 8, M_X = 32, M_TOT = 40, M_PR = 44 };
+static_assert(M_PR + PMW <= 64, "misc slots");
 
 // Presence group of tile-relative position rel is pruned (bit rel / GW of the
-// 128-bit mask; positions outside the tile are never pruned).
-__device__ __forceinline__ bool pruned_at(const uint4& pm, uint32_t rel) {
+// mask; positions outside the tile are never pruned).
+__device__ __forceinline__ bool pruned_at(const PMask& pm, uint32_t rel) {
     const uint32_t g = rel / (uint32_t)GW;
-    const uint32_t w = g < 32u ? pm.x : g < 64u ? pm.y : g < 96u ? pm.z : pm.w;
-    return g < 128u && ((w >> (g & 31u)) & 1u);
+    return g < (uint32_t)NGROUPS && ((pm.w[g >> 5] >> (g & 31u)) & 1u);
 }
 
 // Adds, for every presence group of the tile, the number of this wavefront's
-// inputs (lanes with valid set) that touch it into cnt[g] (LDS).
-__device__ __forceinline__ void count_presence(const uint4& pr, bool valid, uint32_t* cnt) {
+// inputs (lanes with valid set) that touch it into cnt[g] (LDS).  pr: the
+// input's PV presence records.
+__device__ __forceinline__ void count_presence(const uint4* pr, bool valid, uint32_t* cnt) {
     const int lane = __lane_id();
-    const uint64_t lo = valid ? ((uint64_t)pr.y << 32 | pr.x) : 0ull;
-    const uint64_t hi = valid ? ((uint64_t)pr.w << 32 | pr.z) : 0ull;
     if (__ballot(valid) == 0ull) return;
-    uint32_t cl = 0, ch = 0;   // lane g holds the counts of groups g and 64 + g
+#pragma unroll
+    for (int h = 0; h < NGROUPS / 64; ++h) {   // 64 groups at a time
+        const uint4 r = pr[h >> 1];
+        const uint64_t m = !valid ? 0ull : (h & 1) ? ((uint64_t)r.w << 32 | r.z) : ((uint64_t)r.y << 32 | r.x);
+        uint32_t c = 0;   // lane g holds the count of group 64 h + g
 #pragma unroll 8
-    for (int g = 0; g < 64; ++g) {
-        const uint32_t a = (uint32_t)__popcll(__ballot((lo >> g) & 1ull));
-        const uint32_t b = (NGROUPS > 64) ? (uint32_t)__popcll(__ballot((hi >> g) & 1ull)) : 0u;
-        cl = lane == g ? a : cl;
-        ch = lane == g ? b : ch;
+        for (int g = 0; g < 64; ++g) {
+            const uint32_t a = (uint32_t)__popcll(__ballot((m >> g) & 1ull));
+            c = lane == g ? a : c;
+        }
+        if (c) atomicAdd(&cnt[64 * h + lane], c);
     }
-    if (cl) atomicAdd(&cnt[lane], cl);
-    if (NGROUPS > 64 && ch) atomicAdd(&cnt[64 + lane], ch);
 }
 
 // Window list entry (16 bytes, one per 64-word window):
@@ -443,17 +451,20 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     EWT_PHASE(0);
     for (int i = tid; i < P * TW; i += BLOCK) planes[i] = 0;
     for (int i = tid; i < TW + 8; i += BLOCK) diff[i] = 0;
-    uint32_t* gcnt = (uint32_t*)win;   // presence counts per group (the window list is not in use yet)
-    if (tid < NGROUPS) gcnt[tid] = 0;
+    // until the decode starts, the window list holds the presence words of the
+    // first PCAP inputs (word-major: word w of input k at w * PCAP + k) and the
+    // dense-row list the per-group counts
+    uint32_t* prs = (uint32_t*)win;
+    constexpr uint32_t PCAP = (uint32_t)(WCAP / PV);
+    uint32_t* gcnt = (uint32_t*)dense;
     if (tid < 8) misc[tid] = 0;
-    if (tid < 4) misc[M_PR + tid] = 0;
+    if (tid < PMW) misc[M_PR + tid] = 0;
     __syncthreads();
 
     // ---- classify / prune (RBMrg on EWAH, cases 1 and 2, per tile)
     const bool trivial = (T == 0) || (T > N);
     Seg seg;
     BitmapDev B0;
-    uint4 pr0 = make_uint4(0u, 0u, 0u, 0u);
     const uint32_t ngv = (nPos + (uint32_t)GW - 1u) / (uint32_t)GW;   // presence groups inside the tile
     if (!trivial) {
         for (uint32_t kb = 0; kb < N; kb += BLOCK) {
@@ -462,12 +473,21 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             uint32_t np = 0;
             if (k < N) {
                 const BitmapDev B = gp(table)[gp(q.ids)[k]];
-                const uint4 pr = gp(B.pres)[t];
+#pragma unroll
+                for (int v = 0; v < PV; ++v) {
+                    const uint4 pr = gp(B.pres)[(size_t)t * PV + v];
+                    np += (uint32_t)(__popc(pr.x) + __popc(pr.y) + __popc(pr.z) + __popc(pr.w));
+                    if (k < PCAP) {
+                        prs[(4 * v) * PCAP + k] = pr.x;
+                        prs[(4 * v + 1) * PCAP + k] = pr.y;
+                        prs[(4 * v + 2) * PCAP + k] = pr.z;
+                        prs[(4 * v + 3) * PCAP + k] = pr.w;
+                    }
+                }
                 Seg s = locate(B, t, tS, tE, tiles);
                 onefull = s.onefull;
                 nonzero = !s.zero;
-                np = (uint32_t)(__popc(pr.x) + __popc(pr.y) + __popc(pr.z) + __popc(pr.w));
-                if (kb == 0) { seg = s; B0 = B; pr0 = pr; }
+                if (kb == 0) { seg = s; B0 = B; }
             }
             // one LDS atomic per wavefront and counter
             const uint32_t c1 = (uint32_t)__popcll(__ballot(onefull)), c2 = (uint32_t)__popcll(__ballot(nonzero));
@@ -487,13 +507,52 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                             : (misc[M_ONEFULL] >= T ? 1u : (misc[M_NONZERO] < T ? 2u : 0u));
     // per-group bounds: counted only when fewer than T inputs touch every group and
     // T is above 9/10 of the mean bound (else few groups, if any, fall below T)
-    uint4 pm = make_uint4(0u, 0u, 0u, 0u);
+    PMask pm;
+    pm.w = misc + M_PR;
+    pm.on = false;
     if (mode == 0 && misc[M_DFULL] < T && 10ull * T * ngv > 9ull * misc[M_PSUM]) {
-        for (uint32_t kb = 0; kb < N; kb += BLOCK) {
-            const uint32_t k = kb + (uint32_t)tid;
-            uint4 pr = pr0;
-            if (kb != 0 && k < N) pr = gp(gp(table)[gp(q.ids)[k]].pres)[t];
-            count_presence(pr, k < N, gcnt);
+        // staged inputs: QS lanes per quad of groups (BLOCK = NGROUPS / 4 * QS), each
+        // counting every QS-th input.  A lane keeps the four counts in the bytes of one
+        // word: the quad's four bits are spread to bits 0, 8, 16, 24 by one multiply
+        // (x * (1 + 2^7 + 2^14 + 2^21): the four shifted copies do not overlap) and
+        // added; a lane sees at most PCAP / QS <= 64 inputs, so no byte overflows.
+        // Then the counts are widened to 16-bit halves and summed over the quad's lanes.
+        {
+            constexpr uint32_t QS = 4u * GW;
+            static_assert(PCAP / QS < 256u && (NGROUPS / 4) * QS == BLOCK && QS <= 64u, "quad counters");
+            const uint32_t qd = (uint32_t)tid / QS, j = (uint32_t)tid % QS;
+            const uint32_t* p32 = prs + (qd >> 3) * PCAP;
+            const uint32_t sh = (qd & 7u) * 4u, ns = min(N, PCAP);
+            uint32_t c = 0;
+#pragma unroll 4
+            for (uint32_t k = j; k < ns; k += QS) c += (((p32[k] >> sh) & 15u) * 0x00204081u) & 0x01010101u;
+            uint32_t c02 = c & 0x00FF00FFu, c13 = (c >> 8) & 0x00FF00FFu;   // groups 0, 2 and 1, 3 of the quad
+#pragma unroll
+            for (uint32_t o = 1; o < QS; o <<= 1) {
+                c02 += (uint32_t)__shfl_xor((int)c02, (int)o);
+                c13 += (uint32_t)__shfl_xor((int)c13, (int)o);
+            }
+            if (j == 0) {
+                gcnt[4 * qd] = c02 & 0xFFFFu;
+                gcnt[4 * qd + 1] = c13 & 0xFFFFu;
+                gcnt[4 * qd + 2] = c02 >> 16;
+                gcnt[4 * qd + 3] = c13 >> 16;
+            }
+        }
+        if (N > PCAP) {   // the rest (very wide queries): wavefront ballots into the counts
+            __syncthreads();
+            for (uint32_t kb = PCAP; kb < N; kb += BLOCK) {
+                const uint32_t k = kb + (uint32_t)tid;
+                uint4 pr[PV];
+#pragma unroll
+                for (int v = 0; v < PV; ++v) pr[v] = make_uint4(0u, 0u, 0u, 0u);
+                if (k < N) {
+                    const uint4* src = gp(gp(table)[gp(q.ids)[k]].pres) + (size_t)t * PV;
+#pragma unroll
+                    for (int v = 0; v < PV; ++v) pr[v] = src[v];
+                }
+                count_presence(pr, k < N, gcnt);
+            }
         }
         __syncthreads();
         if (tid < NGROUPS) {
@@ -501,10 +560,13 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             if ((tid & 63) == 0) { misc[M_PR + 2 * (tid >> 6)] = (uint32_t)m; misc[M_PR + 2 * (tid >> 6) + 1] = (uint32_t)(m >> 32); }
         }
         __syncthreads();
-        pm = make_uint4(misc[M_PR], misc[M_PR + 1], misc[M_PR + 2], misc[M_PR + 3]);
-        if ((uint32_t)(__popc(pm.x) + __popc(pm.y) + __popc(pm.z) + __popc(pm.w)) == ngv) mode = 2u;
+        uint32_t npr = 0;
+#pragma unroll
+        for (int i = 0; i < PMW; ++i) npr += (uint32_t)__popc(misc[M_PR + i]);
+        pm.on = npr != 0u;
+        if (npr == ngv) mode = 2u;
     }
-    const bool prune = (pm.x | pm.y | pm.z | pm.w) != 0u;
+    const bool prune = pm.any();
 
     // ---- decode and count
     if (mode == 0) {
