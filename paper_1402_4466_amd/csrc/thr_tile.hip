@@ -20,13 +20,34 @@ __device__ __forceinline__ EWT_GLOBAL T* gp(T* p) {
 
 // ------------------------------------------------------------ wave helpers
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = __lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
+// Inclusive prefix sum across the 64 lanes with DPP row shifts and row
+// broadcasts (no LDS traffic): shifts by 1, 2, 4, 8 inside each row of 16
+// lanes, then lane 15 of each row is added to the next row and lane 31 to the
+// upper two rows.
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) { return wave_incl_scan_dpp(v); }
+
+// Sum over aligned groups of G consecutive lanes (G = 16, 32 or 64), left in the
+// group's last lane: windowed shifts inside each row of 16 lanes, then row
+// broadcasts join the rows of a group.
+template <int G>
+__device__ __forceinline__ uint32_t group_sum_dpp(uint32_t v) {
+    static_assert(G == 16 || G == 32 || G == 64, "group of lanes");
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    if (G >= 32) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    if (G >= 64) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);   // row_bcast:31
     return v;
 }
 
@@ -217,20 +238,6 @@ __device__ __forceinline__ void lit_lane(const EWT_GLOBAL uint64_t* words, uint3
             if (g0 + (uint32_t)i < cnt && !(prune && pruned_at(pm, p0 + g0 + (uint32_t)i)))
                 ripple_add(planes, p0 + g0 + (uint32_t)i, w[i], P);
     }
-}
-
-// Inclusive prefix sum across the 64 lanes with DPP row shifts and row
-// broadcasts (no LDS traffic): shifts by 1, 2, 4, 8 inside each row of 16
-// lanes, then lane 15 of each row is added to the next row and lane 31 to the
-// upper two rows.
-__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v) {
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);   // row_shr:1
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);   // row_shr:2
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);   // row_shr:8
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);   // row_bcast:15
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);   // row_bcast:31
-    return v;
 }
 
 // Per-lane select by a wave-uniform lane mask held in scalar registers:
@@ -519,20 +526,17 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         // Then the counts are widened to 16-bit halves and summed over the quad's lanes.
         {
             constexpr uint32_t QS = 4u * GW;
-            static_assert(PCAP / QS < 256u && (NGROUPS / 4) * QS == BLOCK && QS <= 64u, "quad counters");
+            static_assert(PCAP / QS < 256u && (NGROUPS / 4) * QS == BLOCK && QS >= 16u && QS <= 64u, "quad counters");
             const uint32_t qd = (uint32_t)tid / QS, j = (uint32_t)tid % QS;
             const uint32_t* p32 = prs + (qd >> 3) * PCAP;
             const uint32_t sh = (qd & 7u) * 4u, ns = min(N, PCAP);
             uint32_t c = 0;
 #pragma unroll 4
             for (uint32_t k = j; k < ns; k += QS) c += (((p32[k] >> sh) & 15u) * 0x00204081u) & 0x01010101u;
-            uint32_t c02 = c & 0x00FF00FFu, c13 = (c >> 8) & 0x00FF00FFu;   // groups 0, 2 and 1, 3 of the quad
-#pragma unroll
-            for (uint32_t o = 1; o < QS; o <<= 1) {
-                c02 += (uint32_t)__shfl_xor((int)c02, (int)o);
-                c13 += (uint32_t)__shfl_xor((int)c13, (int)o);
-            }
-            if (j == 0) {
+            // groups 0, 2 and 1, 3 of the quad; sums over the quad's lanes stay below 2^16
+            const uint32_t c02 = group_sum_dpp<QS>(c & 0x00FF00FFu);
+            const uint32_t c13 = group_sum_dpp<QS>((c >> 8) & 0x00FF00FFu);
+            if (j == QS - 1u) {
                 gcnt[4 * qd] = c02 & 0xFFFFu;
                 gcnt[4 * qd + 1] = c13 & 0xFFFFu;
                 gcnt[4 * qd + 2] = c02 >> 16;
@@ -1100,7 +1104,9 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __r
             s_q = qi;
         }
         __syncthreads();
-        const uint32_t it = s_item, qi = s_q;
+        // uniform: the query record is then read into scalar registers
+        const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_item);
+        const uint32_t qi = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_q);
         if (it >= total) break;
         QueryDev q = qs[qi];
         process_tile<true>(q, table, it - qtile[qi], epoch, smem, err, it);
