@@ -177,10 +177,6 @@ __device__ __forceinline__ Seg locate(const BitmapDev& B, uint32_t t, uint32_t t
     return s;
 }
 
-// One lane decodes the compressed words [bs, be) (bs is a marker whose run
-// starts at y0) and adds whatever falls inside [tS, tE).  Words are read eight
-// at a time; streams are padded so reads up to CHUNK words past the end stay
-// inside the allocation.
 // Groups of a tile whose count bound is below T: bit g of the NGROUPS-bit mask
 // in LDS (PMW words at w), read only where some group is pruned.
 struct PMask {
@@ -190,6 +186,10 @@ struct PMask {
 };
 __device__ __forceinline__ bool pruned_at(const PMask& pm, uint32_t rel);
 
+// One lane decodes the compressed words [bs, be) (bs is a marker whose run
+// starts at y0) and adds whatever falls inside [tS, tE).  Words are read eight
+// at a time; streams are padded so reads up to CHUNK words past the end stay
+// inside the allocation.
 __device__ __forceinline__ void walk_lane(const EWT_GLOBAL uint64_t* words, uint32_t bs, uint32_t be, uint32_t y0,
                                           uint32_t tS, uint32_t tE, uint64_t* planes, int32_t* diff, int P,
                                           const PMask& pm) {
@@ -667,38 +667,36 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                         for (int g = 0; g < WIN_BATCH; ++g) lit[g] &= ~__ballot(pruned_at(pm, r[g] - tS));
                     }
                     // dirty words in range add at their tile-relative position
-                    uint32_t act = 0;   // bit g: window g still carries somewhere
+                    uint32_t act = 0;   // bit g: window g has a word to add
 #pragma unroll
                     for (int g = 0; g < WIN_BATCH; ++g) {
-                        r[g] -= tS;
+                        r[g] = lane_sel(lit[g], (uint32_t)lane, r[g] - tS);   // lanes without a word: distinct in-tile slots
                         x[g] = lane_sel64(lit[g], 0ull, x[g]);
                         if (lit[g]) act |= 1u << g;
                     }
                     // next batch's loads
                     if (w0 + (uint32_t)WIN_BATCH < we) issue_batch(win, w0 + (uint32_t)WIN_BATCH, we, lane, sk, v, fl);
-                    // ripple-carry adds, one plane at a time: all atomics of a plane are
-                    // issued before any result is used; a window drops out once none of
-                    // its lanes carries
-                    for (int p = 0; p < P && act; ++p) {
-                        uint64_t old[WIN_BATCH];
+                    // ripple-carry adds, one plane at a time over the whole batch: all atomics
+                    // of a plane are issued before any result is used, and the batch leaves
+                    // once no lane carries (no per-window bookkeeping)
+                    if (act) {
+                        for (int p = 0; p < P; ++p) {
+                            uint64_t old[WIN_BATCH];
 #pragma unroll
-                        for (int g = 0; g < WIN_BATCH; ++g) {
-                            old[g] = 0;
-                            if (act & (1u << g))
+                            for (int g = 0; g < WIN_BATCH; ++g) {
                                 old[g] = atomicXor((unsigned long long*)&planes[p * TW + r[g]], (unsigned long long)x[g]);
-                        }
-                        // one wait for all of them (lgkmcnt(0)); without it the compiler cannot tell
-                        // that no result is still in flight at the next plane and waits per atomic
-                        __builtin_amdgcn_s_waitcnt(0xC07F);
-                        uint32_t nact = 0;
-#pragma unroll
-                        for (int g = 0; g < WIN_BATCH; ++g) {
-                            if (act & (1u << g)) {
-                                x[g] &= old[g];
-                                if (__ballot(x[g] != 0ull)) nact |= 1u << g;
                             }
+                            // one wait for all of them (lgkmcnt(0)); without it the compiler cannot
+                            // tell that no result is still in flight and waits per atomic
+                            __builtin_amdgcn_s_waitcnt(0xC07F);
+                            uint64_t any = 0;
+#pragma unroll
+                            for (int g = 0; g < WIN_BATCH; ++g) {
+                                x[g] &= old[g];
+                                any |= x[g];
+                            }
+                            if (__ballot(any != 0ull) == 0ull) break;
                         }
-                        act = nact;
                     }
                 }
                 __syncthreads();
