@@ -14,10 +14,11 @@
 //      that can hold a one in the tile are counted; the three cases of RBMrg on
 //      EWAH (Section 6.4) at tile granularity: >= T full one-fills -> all ones,
 //      fewer than T non-empty inputs -> all zeros, else count.  The second case
-//      is also applied per group of GW words: the number of inputs holding a
+//      is also applied per group of words: the number of inputs holding a
 //      dirty word or a one-fill in the group bounds every row count there, so
 //      groups whose bound is below T are all zeros and nothing is added there
-//      (registration stores which groups each input touches);
+//      (registration stores which words and which 4-word groups each input
+//      touches; queries of up to 256 inputs take single words);
 //   3. decode: short segments are walked by one lane (eight words per read);
 //      long ones are cut into 64-word windows aligned to the compressed
 //      stream, listed in LDS and shared out among the wavefronts, each window
@@ -55,19 +56,21 @@ namespace ewt {
 constexpr int TW = EWT_TILE_WORDS;    // tile width in uncompressed 64-bit words (= locator granularity)
 constexpr int BLOCK = EWT_TILE_WORDS; // threads per workgroup (one per word position of a tile)
 constexpr int NWAVES = BLOCK / 64;
-#ifndef EWT_GROUP_WORDS
-#define EWT_GROUP_WORDS 4         // words per presence group (host and device must agree)
-#endif
-constexpr int GW = EWT_GROUP_WORDS;   // words per presence group (upper bounds on row counts)
-constexpr int NGROUPS = TW / GW;      // presence groups per tile
-constexpr int PMW = NGROUPS / 32;     // 32-bit words of a tile's group mask
-constexpr int PV = (NGROUPS + 127) / 128;   // 16-byte presence records per tile and bitmap
-static_assert(NGROUPS >= 64 && NGROUPS <= 256 && NGROUPS % 64 == 0 && TW % GW == 0, "presence groups per tile");
+// Presence records (upper bounds on row counts): which groups of words of a tile an
+// input touches.  Two granularities are kept: single words, used by queries of up to
+// PCAP_FINE inputs, and groups of 4 words, used by wider queries.
+constexpr int GW_COARSE = 4;
+constexpr int NG_FINE = TW;                   // groups per tile, single words
+constexpr int NG_COARSE = TW / GW_COARSE;     // groups per tile, 4-word groups
+constexpr int PV_FINE = NG_FINE / 128;        // 16-byte records per tile and bitmap
+constexpr int PV_COARSE = NG_COARSE / 128;
+constexpr int PMW_MAX = NG_FINE / 32;         // 32-bit words of the largest group mask
+static_assert(TW % 512 == 0 && NG_FINE <= BLOCK, "presence groups per tile");
 constexpr int CHUNK = 64;         // compressed words per skip-index entry (one wavefront)
 constexpr int MAXP = 12;          // bit planes: inputs per query < 2^12 (LDS budget)
 constexpr uint32_t MAXN = (1u << MAXP) - 1;
 
-// Registered bitmap as seen by the kernels (48 bytes).
+// Registered bitmap as seen by the kernels (56 bytes).
 struct BitmapDev {
     const uint64_t* words;   // EWAH stream, zero-padded to a multiple of CHUNK words plus CHUNK more
                              // (reads up to CHUNK words past the end stay inside the allocation)
@@ -77,9 +80,10 @@ struct BitmapDev {
                              // uncompressed position where word 64c's coverage starts, 0}
     uint32_t n_words;
     uint32_t U;              // uncompressed words
-    const uint4* pres;       // per tile PV records: bit g (of NGROUPS) set iff words [GW g, GW g + GW)
-                             // of the tile hold a dirty word or a one-fill (the input can contribute
-                             // to those rows)
+    const uint4* pres;       // per tile PV_COARSE records: bit g set iff words [4g, 4g + 4) of the
+                             // tile hold a dirty word or a one-fill (the input can contribute there)
+    const uint4* pres1;      // per tile PV_FINE records: bit w set iff word w of the tile is a dirty
+                             // word or lies in a one-fill
 };
 
 // Associative run-structure aggregate of a range of output words (see encode step).
@@ -136,6 +140,7 @@ __host__ __device__ inline int planes_for(uint32_t n) {
 }
 
 constexpr int WCAP = 2 * BLOCK;   // cooperative windows listed in LDS per round
+constexpr int MISC_WORDS = 128;   // LDS counters and scratch of the tile routine
 constexpr int STAGE_WORDS = TW + 8;   // staged output words per tile (at most TW + 1 are used)
 
 // LDS bytes needed by the tile routine for a query with N inputs.
@@ -145,7 +150,7 @@ __host__ __device__ inline size_t tile_smem_bytes(uint32_t N) {
     b += (TW + 8) * 4;                     // one-fill difference array (+ pad)
     b += (size_t)WCAP * 16;                // window list
     b += BLOCK * 8;                        // dense row pointers
-    b += 64 * 4;                           // misc counters / scan scratch
+    b += MISC_WORDS * 4;                   // misc counters / scan scratch / group mask
     return b;
 }
 

@@ -36,16 +36,16 @@ __device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v) {
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) { return wave_incl_scan_dpp(v); }
 
-// Sum over aligned groups of G consecutive lanes (G = 16, 32 or 64), left in the
-// group's last lane: windowed shifts inside each row of 16 lanes, then row
-// broadcasts join the rows of a group.
+// Sum over aligned groups of G consecutive lanes (G = 4, 8, 16, 32 or 64), left in
+// the group's last lane: windowed shifts inside each row of 16 lanes (a window of G
+// lanes after log2 G shifts), then row broadcasts join the rows of a group.
 template <int G>
 __device__ __forceinline__ uint32_t group_sum_dpp(uint32_t v) {
-    static_assert(G == 16 || G == 32 || G == 64, "group of lanes");
+    static_assert(G == 4 || G == 8 || G == 16 || G == 32 || G == 64, "group of lanes");
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);   // row_shr:1
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);   // row_shr:2
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    if (G >= 8) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    if (G >= 16) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
     if (G >= 32) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);   // row_bcast:15
     if (G >= 64) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);   // row_bcast:31
     return v;
@@ -177,10 +177,12 @@ __device__ __forceinline__ Seg locate(const BitmapDev& B, uint32_t t, uint32_t t
     return s;
 }
 
-// Groups of a tile whose count bound is below T: bit g of the NGROUPS-bit mask
-// in LDS (PMW words at w), read only where some group is pruned.
+// Groups of a tile whose count bound is below T: bit g of the ng-bit mask in LDS
+// (words at w; group g covers the words [g << sh, (g + 1) << sh) of the tile), read
+// only where some group is pruned.
 struct PMask {
     const uint32_t* w;
+    uint32_t sh, ng;
     bool on;
     __device__ bool any() const { return on; }
 };
@@ -339,24 +341,24 @@ __device__ uint64_t* ewt_phase_buf;
 #endif
 
 // Misc LDS slots.
-enum { M_NDENSE = 1, M_PSUM = 2, M_ONEFULL = 4, M_NONZERO = 5, M_DFULL = 6, M_TMP = 8, M_X = 32, M_TOT = 40, M_PR = 44 };
-static_assert(M_PR + PMW <= 64, "misc slots");
+enum { M_NDENSE = 1, M_PSUM = 2, M_ONEFULL = 4, M_NONZERO = 5, M_DFULL = 6, M_TMP = 8, M_X = 32, M_TOT = 40, M_PR = 64 };
+static_assert(M_PR + PMW_MAX <= MISC_WORDS, "misc slots");
 
-// Presence group of tile-relative position rel is pruned (bit rel / GW of the
-// mask; positions outside the tile are never pruned).
+// Presence group of tile-relative position rel is pruned (positions outside the
+// tile are never pruned).
 __device__ __forceinline__ bool pruned_at(const PMask& pm, uint32_t rel) {
-    const uint32_t g = rel / (uint32_t)GW;
-    return g < (uint32_t)NGROUPS && ((pm.w[g >> 5] >> (g & 31u)) & 1u);
+    const uint32_t g = rel >> pm.sh;
+    return g < pm.ng && ((pm.w[g >> 5] >> (g & 31u)) & 1u);
 }
 
-// Adds, for every presence group of the tile, the number of this wavefront's
-// inputs (lanes with valid set) that touch it into cnt[g] (LDS).  pr: the
-// input's PV presence records.
+// Adds, for every 4-word group of the tile, the number of this wavefront's inputs
+// (lanes with valid set) that touch it into cnt[g] (LDS).  pr: the input's
+// PV_COARSE presence records.
 __device__ __forceinline__ void count_presence(const uint4* pr, bool valid, uint32_t* cnt) {
     const int lane = __lane_id();
     if (__ballot(valid) == 0ull) return;
 #pragma unroll
-    for (int h = 0; h < NGROUPS / 64; ++h) {   // 64 groups at a time
+    for (int h = 0; h < NG_COARSE / 64; ++h) {   // 64 groups at a time
         const uint4 r = pr[h >> 1];
         const uint64_t m = !valid ? 0ull : (h & 1) ? ((uint64_t)r.w << 32 | r.z) : ((uint64_t)r.y << 32 | r.x);
         uint32_t c = 0;   // lane g holds the count of group 64 h + g
@@ -432,6 +434,40 @@ __device__ __forceinline__ void issue_batch(const uint4* win, uint32_t w0, uint3
     }
 }
 
+// Per-group input counts from presence words staged in LDS word-major (word w of
+// input k at w * pcap + k) for the first ns inputs.  QS lanes share a quad of groups
+// (BLOCK = groups / 4 * QS), each counting every QS-th input.  A lane keeps the four
+// counts in the bytes of one word: the quad's four bits are spread to bits 0, 8, 16
+// and 24 by one multiply (x * (1 + 2^7 + 2^14 + 2^21): the shifted copies do not
+// overlap) and added; a lane sees at most pcap / QS <= 64 inputs, so no byte
+// overflows.  The counts are then widened to 16-bit halves and summed over the quad's
+// lanes.
+template <int QS>
+__device__ __forceinline__ void count_quads(const uint32_t* prs, uint32_t pcap, uint32_t ns, uint32_t* gcnt) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t qd = tid / (uint32_t)QS, j = tid % (uint32_t)QS;
+    const uint32_t* p32 = prs + (qd >> 3) * pcap;
+    const uint32_t sh = (qd & 7u) * 4u;
+    uint32_t c = 0;
+#pragma unroll 4
+    for (uint32_t k = j; k < ns; k += (uint32_t)QS) c += (((p32[k] >> sh) & 15u) * 0x00204081u) & 0x01010101u;
+    // groups 0, 2 and 1, 3 of the quad; sums over the quad's lanes stay below 2^16
+    const uint32_t c02 = group_sum_dpp<QS>(c & 0x00FF00FFu);
+    const uint32_t c13 = group_sum_dpp<QS>((c >> 8) & 0x00FF00FFu);
+    if (j == (uint32_t)QS - 1u) {
+        gcnt[4 * qd] = c02 & 0xFFFFu;
+        gcnt[4 * qd + 1] = c13 & 0xFFFFu;
+        gcnt[4 * qd + 2] = c02 >> 16;
+        gcnt[4 * qd + 3] = c13 >> 16;
+    }
+}
+
+// Staged inputs per granularity (the window list holds 16 * WCAP bytes).
+constexpr uint32_t PCAP_FINE = (uint32_t)(WCAP / PV_FINE);
+constexpr uint32_t PCAP_COARSE = (uint32_t)(WCAP / PV_COARSE);
+static_assert((NG_FINE / 4) * 4 == BLOCK && (NG_COARSE / 4) * 16 == BLOCK, "lanes per quad of groups");
+static_assert(PCAP_FINE / 4 < 256u && PCAP_COARSE / 16 < 256u, "byte counters");
+
 // STAGED: the tile writes its words to the staging area and publishes its
 // aggregate (a placement pass finishes the output); otherwise it finds the prefix
 // over earlier tiles by look-back and writes its words in place.
@@ -459,20 +495,26 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     for (int i = tid; i < P * TW; i += BLOCK) planes[i] = 0;
     for (int i = tid; i < TW + 8; i += BLOCK) diff[i] = 0;
     // until the decode starts, the window list holds the presence words of the
-    // first PCAP inputs (word-major: word w of input k at w * PCAP + k) and the
+    // first pcap inputs (word-major: word w of input k at w * pcap + k) and the
     // dense-row list the per-group counts
     uint32_t* prs = (uint32_t*)win;
-    constexpr uint32_t PCAP = (uint32_t)(WCAP / PV);
     uint32_t* gcnt = (uint32_t*)dense;
     if (tid < 8) misc[tid] = 0;
-    if (tid < PMW) misc[M_PR + tid] = 0;
+    if (tid < PMW_MAX) misc[M_PR + tid] = 0;
     __syncthreads();
 
     // ---- classify / prune (RBMrg on EWAH, cases 1 and 2, per tile)
     const bool trivial = (T == 0) || (T > N);
     Seg seg;
     BitmapDev B0;
-    const uint32_t ngv = (nPos + (uint32_t)GW - 1u) / (uint32_t)GW;   // presence groups inside the tile
+    // presence granularity: single words for queries of up to PCAP_FINE inputs, else
+    // groups of 4 words
+    const bool fine = N <= PCAP_FINE;
+    const uint32_t gsh = fine ? 0u : 2u;   // log2 of the words per group
+    const uint32_t ng = fine ? (uint32_t)NG_FINE : (uint32_t)NG_COARSE;
+    const uint32_t pv = fine ? (uint32_t)PV_FINE : (uint32_t)PV_COARSE;
+    const uint32_t pcap = fine ? PCAP_FINE : PCAP_COARSE;
+    const uint32_t ngv = (nPos + (1u << gsh) - 1u) >> gsh;   // groups inside the tile
     if (!trivial) {
         for (uint32_t kb = 0; kb < N; kb += BLOCK) {
             uint32_t k = kb + (uint32_t)tid;
@@ -480,15 +522,18 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             uint32_t np = 0;
             if (k < N) {
                 const BitmapDev B = gp(table)[gp(q.ids)[k]];
+                const uint4* src = (fine ? B.pres1 : B.pres) + (size_t)t * pv;
 #pragma unroll
-                for (int v = 0; v < PV; ++v) {
-                    const uint4 pr = gp(B.pres)[(size_t)t * PV + v];
-                    np += (uint32_t)(__popc(pr.x) + __popc(pr.y) + __popc(pr.z) + __popc(pr.w));
-                    if (k < PCAP) {
-                        prs[(4 * v) * PCAP + k] = pr.x;
-                        prs[(4 * v + 1) * PCAP + k] = pr.y;
-                        prs[(4 * v + 2) * PCAP + k] = pr.z;
-                        prs[(4 * v + 3) * PCAP + k] = pr.w;
+                for (int v = 0; v < PV_FINE; ++v) {
+                    if ((uint32_t)v < pv) {
+                        const uint4 pr = gp(src)[v];
+                        np += (uint32_t)(__popc(pr.x) + __popc(pr.y) + __popc(pr.z) + __popc(pr.w));
+                        if (k < pcap) {
+                            prs[(4 * v) * pcap + k] = pr.x;
+                            prs[(4 * v + 1) * pcap + k] = pr.y;
+                            prs[(4 * v + 2) * pcap + k] = pr.z;
+                            prs[(4 * v + 3) * pcap + k] = pr.w;
+                        }
                     }
                 }
                 Seg s = locate(B, t, tS, tE, tiles);
@@ -516,57 +561,37 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     // T is above 9/10 of the mean bound (else few groups, if any, fall below T)
     PMask pm;
     pm.w = misc + M_PR;
+    pm.sh = gsh;
+    pm.ng = ng;
     pm.on = false;
     if (mode == 0 && misc[M_DFULL] < T && 10ull * T * ngv > 9ull * misc[M_PSUM]) {
-        // staged inputs: QS lanes per quad of groups (BLOCK = NGROUPS / 4 * QS), each
-        // counting every QS-th input.  A lane keeps the four counts in the bytes of one
-        // word: the quad's four bits are spread to bits 0, 8, 16, 24 by one multiply
-        // (x * (1 + 2^7 + 2^14 + 2^21): the four shifted copies do not overlap) and
-        // added; a lane sees at most PCAP / QS <= 64 inputs, so no byte overflows.
-        // Then the counts are widened to 16-bit halves and summed over the quad's lanes.
-        {
-            constexpr uint32_t QS = 4u * GW;
-            static_assert(PCAP / QS < 256u && (NGROUPS / 4) * QS == BLOCK && QS >= 16u && QS <= 64u, "quad counters");
-            const uint32_t qd = (uint32_t)tid / QS, j = (uint32_t)tid % QS;
-            const uint32_t* p32 = prs + (qd >> 3) * PCAP;
-            const uint32_t sh = (qd & 7u) * 4u, ns = min(N, PCAP);
-            uint32_t c = 0;
-#pragma unroll 4
-            for (uint32_t k = j; k < ns; k += QS) c += (((p32[k] >> sh) & 15u) * 0x00204081u) & 0x01010101u;
-            // groups 0, 2 and 1, 3 of the quad; sums over the quad's lanes stay below 2^16
-            const uint32_t c02 = group_sum_dpp<QS>(c & 0x00FF00FFu);
-            const uint32_t c13 = group_sum_dpp<QS>((c >> 8) & 0x00FF00FFu);
-            if (j == QS - 1u) {
-                gcnt[4 * qd] = c02 & 0xFFFFu;
-                gcnt[4 * qd + 1] = c13 & 0xFFFFu;
-                gcnt[4 * qd + 2] = c02 >> 16;
-                gcnt[4 * qd + 3] = c13 >> 16;
-            }
-        }
-        if (N > PCAP) {   // the rest (very wide queries): wavefront ballots into the counts
+        if (fine) count_quads<4>(prs, PCAP_FINE, min(N, PCAP_FINE), gcnt);
+        else count_quads<16>(prs, PCAP_COARSE, min(N, PCAP_COARSE), gcnt);
+        if (N > pcap) {   // the rest of very wide queries (4-word groups): wavefront ballots
             __syncthreads();
-            for (uint32_t kb = PCAP; kb < N; kb += BLOCK) {
+            for (uint32_t kb = PCAP_COARSE; kb < N; kb += BLOCK) {
                 const uint32_t k = kb + (uint32_t)tid;
-                uint4 pr[PV];
+                uint4 pr[PV_COARSE];
 #pragma unroll
-                for (int v = 0; v < PV; ++v) pr[v] = make_uint4(0u, 0u, 0u, 0u);
+                for (int v = 0; v < PV_COARSE; ++v) pr[v] = make_uint4(0u, 0u, 0u, 0u);
                 if (k < N) {
-                    const uint4* src = gp(gp(table)[gp(q.ids)[k]].pres) + (size_t)t * PV;
+                    const uint4* src = gp(gp(table)[gp(q.ids)[k]].pres) + (size_t)t * PV_COARSE;
 #pragma unroll
-                    for (int v = 0; v < PV; ++v) pr[v] = src[v];
+                    for (int v = 0; v < PV_COARSE; ++v) pr[v] = src[v];
                 }
                 count_presence(pr, k < N, gcnt);
             }
         }
         __syncthreads();
-        if (tid < NGROUPS) {
+        if ((uint32_t)tid < ng) {
             const uint64_t m = __ballot(gcnt[tid] < T && (uint32_t)tid < ngv);
             if ((tid & 63) == 0) { misc[M_PR + 2 * (tid >> 6)] = (uint32_t)m; misc[M_PR + 2 * (tid >> 6) + 1] = (uint32_t)(m >> 32); }
         }
         __syncthreads();
         uint32_t npr = 0;
 #pragma unroll
-        for (int i = 0; i < PMW; ++i) npr += (uint32_t)__popc(misc[M_PR + i]);
+        for (int i = 0; i < PMW_MAX; ++i)
+            if ((uint32_t)i < ng / 32u) npr += (uint32_t)__popc(misc[M_PR + i]);
         pm.on = npr != 0u;
         if (npr == ngv) mode = 2u;
     }
