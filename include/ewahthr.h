@@ -77,10 +77,12 @@ const char* ewah_last_error(void);
 /*
  * Registration (data loading, not part of a query; the paper likewise assumes
  * the bitmaps are in memory before a query, Section 2).  Validates the stream,
- * copies it to device memory and builds the per-tile locator (for every 1024
- * uncompressed words, the marker whose run covers that word) and the skip
- * index (for every 64 compressed words, the position of the first word and the
- * offset of the first marker).  v->words is a host pointer if on_device == 0,
+ * copies it to device memory and builds its index: the per-tile locator (for
+ * every tile of 512 uncompressed words, the marker whose run covers the tile's
+ * first word, with that marker word), the skip index (for every 64 compressed
+ * words, which of them are markers and the position of the first one) and the
+ * presence records (per tile, which words and which groups of 4 words hold a
+ * dirty word or lie in a one-fill).  v->words is a host pointer if on_device == 0,
  * else a device pointer; it is only read during the call.  The call is
  * synchronous.  Limits: n_bits < 2^37 (U < 2^31 words).  EFORMAT if the stream
  * is malformed.  *out is owned by the caller until ewah_release().

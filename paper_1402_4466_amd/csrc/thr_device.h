@@ -51,7 +51,7 @@
 namespace ewt {
 
 #ifndef EWT_TILE_WORDS
-#define EWT_TILE_WORDS 1024       // compile-time tile width (host and device must agree)
+#define EWT_TILE_WORDS 512        // compile-time tile width (host and device must agree)
 #endif
 constexpr int TW = EWT_TILE_WORDS;    // tile width in uncompressed 64-bit words (= locator granularity)
 constexpr int BLOCK = EWT_TILE_WORDS; // threads per workgroup (one per word position of a tile)
