@@ -515,7 +515,7 @@ struct ewah_batch {
     uint64_t* d_stage = nullptr;   // STAGE_WORDS per tile of every query
     uint32_t* d_tq = nullptr;      // query of every (query, tile) item
     uint32_t total = 0;            // (query, tile) items
-    uint32_t* d_work = nullptr;    // work counter, epoch
+    uint32_t* d_work = nullptr;    // WORK_WORDS words: epoch at [1], per-XCD item counters
     uint32_t* d_codes = nullptr;   // variant codes for ewah_batch_select
     std::vector<uint32_t> h_codes; // their host copy (upload only on change)
     uint64_t n_bits = 0;
@@ -536,7 +536,7 @@ ewah_status batch_build_graph(ewah_batch* b) {
     if (!b->use_graph) return EWAH_OK;
     if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e1 = launch_bump(b->d_work + 1, b->cap_stream);
+    hipError_t e1 = launch_bump(b->d_work, b->cap_stream);
     hipError_t e2 = launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1,
                                  g.d_err, b->grid, b->smem, b->cap_stream);
     hipError_t e3 = hipStreamEndCapture(b->cap_stream, &b->graph);
@@ -605,8 +605,8 @@ ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, con
     }
     HIPCHK(hipMalloc(&b->d_qtile, (nq + 1) * 4));
     HIPCHK(hipMemcpy(b->d_qtile, qtile.data(), (nq + 1) * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMalloc(&b->d_work, 256));
-    HIPCHK(hipMemset(b->d_work, 0, 256));
+    HIPCHK(hipMalloc(&b->d_work, WORK_WORDS * 4));
+    HIPCHK(hipMemset(b->d_work, 0, WORK_WORDS * 4));
     HIPCHK(hipMalloc(&b->d_codes, 64 * 4));
     b->n_bits = n_bits;
     b->h_qs.resize(nq);
@@ -642,7 +642,7 @@ ewah_status ewah_batch_run(ewah_batch* b, void* hip_stream) {
     if (b->exec) {
         HIPCHK(hipGraphLaunch(b->exec, s));
     } else {
-        HIPCHK(launch_bump(b->d_work + 1, s));
+        HIPCHK(launch_bump(b->d_work, s));
         HIPCHK(launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1, g.d_err,
                             b->grid, b->smem, s));
     }

@@ -141,6 +141,12 @@ __host__ __device__ inline int planes_for(uint32_t n) {
 
 constexpr int WCAP = 2 * BLOCK;   // cooperative windows listed in LDS per round
 constexpr int MISC_WORDS = 128;   // LDS counters and scratch of the tile routine
+
+// Batched launches: work state of WORK_WORDS words.  work[1] = epoch; the item
+// counter of XCD x at work[WORK_CTR + WORK_STRIDE * x] (one 64-byte line each).
+constexpr int NXCD = 8;           // XCDs of the MI355X
+constexpr int WORK_CTR = 16, WORK_STRIDE = 16;
+constexpr int WORK_WORDS = WORK_CTR + WORK_STRIDE * NXCD;
 constexpr int STAGE_WORDS = TW + 8;   // staged output words per tile (at most TW + 1 are used)
 
 // LDS bytes needed by the tile routine for a query with N inputs.
@@ -160,7 +166,7 @@ hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* tic
 hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_t* tq, uint32_t nq, uint32_t total,
                         const BitmapDev* table, uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid,
                         size_t smem, hipStream_t s);
-hipError_t launch_bump(uint32_t* epoch, hipStream_t s);
+hipError_t launch_bump(uint32_t* work, hipStream_t s);   // epoch at work[1], counters cleared
 hipError_t launch_zero_len(uint64_t* out_n, hipStream_t s);
 hipError_t set_smem_limits(size_t max_bytes);
 int batch_blocks_per_cu(size_t smem);   // resident workgroups of the batched kernel per CU

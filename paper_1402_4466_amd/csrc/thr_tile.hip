@@ -1101,8 +1101,12 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_kernel(QueryDev q, const B
     process_tile<false>(q, table, s_t, epoch, smem, err, s_t);
 }
 
-// Many queries in one persistent launch: workgroups take (query, tile) items
-// from a global counter in order.  qtile[i] = first item of query i (qtile[nq] = total).
+// Many queries in one persistent launch.  The (query, tile) items are split into
+// NXCD contiguous ranges, one per XCD (workgroup i runs on XCD i mod NXCD), so that
+// neighbouring tiles of a query, which share the compressed chunk at their boundary,
+// are read through one L2.  A workgroup takes the next item of its own range from
+// that range's counter and, once the range is used up, items of the other ranges in
+// turn.  qtile[i] = first item of query i (qtile[nq] = total).
 __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
                                                           uint32_t nq, const BitmapDev* __restrict__ table,
                                                           uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err) {
@@ -1110,10 +1114,18 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __r
     __shared__ uint32_t s_item, s_q;
     const uint32_t total = qtile[nq];
     const uint32_t epoch = *epoch_ptr;
+    const uint32_t x0 = blockIdx.x % (uint32_t)NXCD;
     while (true) {
         if (threadIdx.x == 0) {
-            uint32_t it = atomicAdd(work, 1u);
-            if (it == total + gridDim.x - 1u) __hip_atomic_store(work, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t it = total;   // none left
+            for (uint32_t d = 0; d < (uint32_t)NXCD; ++d) {
+                const uint32_t x = (x0 + d) % (uint32_t)NXCD;
+                const uint32_t lo = (uint32_t)((uint64_t)total * x / NXCD);
+                const uint32_t hi = (uint32_t)((uint64_t)total * (x + 1u) / NXCD);
+                if (lo == hi) continue;
+                const uint32_t c = atomicAdd(&work[WORK_CTR + WORK_STRIDE * x], 1u);
+                if (c < hi - lo) { it = lo + c; break; }
+            }
             uint32_t qi = 0;
             if (it < total) {
                 uint32_t lo = 0, hi = nq - 1;
@@ -1155,10 +1167,12 @@ __global__ __launch_bounds__(256) void place_batch_kernel(const QueryDev* __rest
 // Next launch tag of a batch; tag 0 (the value of cleared states) is skipped.
 // Every launch of a batch rewrites every tile state, so states older than the
 // previous launch never survive and the 16-bit tag cycle is safe.
-__global__ void bump_epoch_kernel(uint32_t* epoch) {
-    uint32_t e = *epoch + 1u;
+// Before each batched launch: advance the epoch (work[1]) and clear the item counters.
+__global__ void bump_epoch_kernel(uint32_t* work) {
+    uint32_t e = work[1] + 1u;
     if ((e & 0xFFFFu) == 0) e += 1u;
-    *epoch = e;
+    work[1] = e;
+    for (int x = 0; x < NXCD; ++x) work[WORK_CTR + WORK_STRIDE * x] = 0u;
 }
 
 // Output for r = 0 (no words).
@@ -1197,8 +1211,8 @@ hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_bump(uint32_t* epoch, hipStream_t s) {
-    hipLaunchKernelGGL(bump_epoch_kernel, dim3(1), dim3(1), 0, s, epoch);
+hipError_t launch_bump(uint32_t* work, hipStream_t s) {
+    hipLaunchKernelGGL(bump_epoch_kernel, dim3(1), dim3(1), 0, s, work);
     return hipGetLastError();
 }
 
