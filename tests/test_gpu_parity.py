@@ -2,10 +2,13 @@
 
 Every case compares the canonical EWAH output words of the GPU path with the
 oracle's, element by element, on the same seeded inputs.  Inputs cover several
-tiles (1024 uncompressed words each) and a ragged last tile, canonical and
-non-canonical streams, every kernel variant, and the degenerate cases.
+tiles (TW uncompressed words each, read from the kernel header) and a ragged last
+tile, canonical and non-canonical streams, every kernel variant, and the
+degenerate cases.
 """
 import itertools
+import os
+import re
 import sys
 
 import numpy as np
@@ -17,7 +20,10 @@ from tests.ewah_test_util import golden, literal_stream, marker, mixed_stream
 
 pytestmark = pytest.mark.gpu
 
-TW_ROWS = 1024 * 64   # rows per tile
+TW = int(re.search(r"#define EWT_TILE_WORDS (\d+)",
+                   open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                     "paper_1402_4466_amd", "csrc", "thr_device.h")).read()).group(1))
+TW_ROWS = TW * 64   # rows per tile
 
 
 def _say(*a):
@@ -115,10 +121,12 @@ def test_long_runs_across_tiles(G):
     rng = np.random.default_rng(3)
     streams = []
     # one-fill of 3.5 tiles, zero-fill, dirty run of 1.5 tiles, one-fill to the end
+    a, b = 7 * TW // 2, 39 * TW // 8 + 8
+    c = b + 3 * TW // 2
     d = np.zeros(U, dtype=np.uint64)
-    d[: 3584] = np.uint64(2**64 - 1)
-    d[5000: 6536] = rng.integers(1, 2**63, size=1536, dtype=np.uint64)
-    d[6536:] = np.uint64(2**64 - 1)
+    d[: a] = np.uint64(2**64 - 1)
+    d[b: c] = rng.integers(1, 2**63, size=c - b, dtype=np.uint64)
+    d[c:] = np.uint64(2**64 - 1)
     d[-1] &= np.uint64((1 << (r % 64)) - 1)
     streams.append(O.encode(d, r))
     # all ones
