@@ -1,4 +1,5 @@
-"""Brute-force threshold (test infrastructure only): pure Python, bit by bit.
+"""Brute-force threshold and symmetric functions (test infrastructure only): pure
+Python, bit by bit.
 
 Used on tiny inputs to pin the C oracle.  Bitmaps are Python sets of row
 numbers; the threshold result is the set of rows present in at least T of
@@ -15,6 +16,19 @@ def threshold_sets(sets, r: int, T: int) -> set:
             if row in s:
                 count += 1
         if count >= T:
+            out.add(row)
+    return out
+
+
+def symmetric_sets(sets, r: int, f) -> set:
+    """Rows whose count c (sets holding the row) has f[c] true (Section 2, Section 3.2)."""
+    out = set()
+    for row in range(r):
+        count = 0
+        for s in sets:
+            if row in s:
+                count += 1
+        if f[count]:
             out.add(row)
     return out
 

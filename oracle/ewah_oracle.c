@@ -156,3 +156,39 @@ done:
     free(dense);
     return rc;
 }
+
+/*
+ * Symmetric function of the inputs (Section 2: threshold functions are the
+ * symmetric Boolean functions given by "count >= T"; Section 3.2: a symmetric
+ * function depends only on the number of ones among its inputs; Section 5.1:
+ * ScanCount handles any user function from [0, N] to the Booleans).  Same
+ * counting as orc_threshold; output row i is f[counter[i]], where f holds N + 1
+ * entries (0 or non-zero).  Padding rows stay 0.
+ */
+int orc_symmetric(const uint64_t* const* streams, const uint64_t* n_words, uint32_t N, uint64_t n_bits,
+                  const uint8_t* f, uint64_t* out, uint64_t cap, uint64_t* n_out) {
+    if (!f) return ORC_EINVAL;
+    uint64_t U = words_for_bits(n_bits);
+    uint32_t* counter = (uint32_t*)calloc(n_bits ? n_bits : 1, sizeof(uint32_t));
+    uint64_t* dense = (uint64_t*)malloc((U ? U : 1) * sizeof(uint64_t));
+    if (!counter || !dense) { free(counter); free(dense); return ORC_ENOMEM; }
+    int rc = ORC_OK;
+    for (uint32_t k = 0; k < N; ++k) {
+        rc = orc_decode(streams[k], n_words[k], n_bits, dense);
+        if (rc != ORC_OK) goto done;
+        for (uint64_t i = 0; i < U; ++i) {
+            uint64_t v = dense[i];
+            if (v == 0) continue;
+            for (uint64_t b = 0; b < 64; ++b)
+                if ((v >> b) & 1) counter[i * 64 + b] += 1;
+        }
+    }
+    for (uint64_t i = 0; i < U; ++i) dense[i] = 0;
+    for (uint64_t row = 0; row < n_bits; ++row)
+        if (f[counter[row]]) dense[row / 64] |= (uint64_t)1 << (row % 64);
+    rc = orc_encode(dense, n_bits, out, cap, n_out);
+done:
+    free(counter);
+    free(dense);
+    return rc;
+}

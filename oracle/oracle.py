@@ -10,6 +10,8 @@ Functions follow the paper's definitions:
   threshold  -- ScanCount T-of-N threshold (Section 2 definition, Section 5.1
                 method), returns the canonical EWAH result and the count
                 histogram
+  symmetric  -- the same counting with any function of the count (Sections 2,
+                3.2 and 5.1), returns the canonical EWAH result
 """
 from __future__ import annotations
 
@@ -50,6 +52,8 @@ def _load():
         L.orc_encode.argtypes = [vp, u64, vp, u64, vp]
         L.orc_threshold.restype = ctypes.c_int
         L.orc_threshold.argtypes = [vp, vp, u32, u64, u32, vp, u64, vp, vp]
+        L.orc_symmetric.restype = ctypes.c_int
+        L.orc_symmetric.argtypes = [vp, vp, u32, u64, vp, vp, u64, vp]
         _lib = L
     return _lib
 
@@ -103,3 +107,24 @@ def threshold(streams, n_bits: int, T: int, want_hist: bool = True):
     if rc != OK:
         raise OracleError(rc, "threshold")
     return out[: n.value].copy(), hist
+
+
+def symmetric(streams, n_bits: int, f):
+    """Canonical EWAH words of the rows whose count c (inputs with the row set) has f[c] true;
+    f has len(streams) + 1 entries."""
+    arrs = [_u64(s) for s in streams]
+    N = len(arrs)
+    if len(f) != N + 1:
+        raise ValueError("f needs N + 1 entries")
+    ptrs = (ctypes.c_void_p * max(N, 1))(*[a.ctypes.data for a in arrs])
+    nws = np.array([len(a) for a in arrs] or [0], dtype=np.uint64)
+    tab = np.array([1 if v else 0 for v in f], dtype=np.uint8)
+    U = (n_bits + 63) // 64
+    cap = U + 1
+    out = np.zeros(max(cap, 1), dtype=np.uint64)
+    n = ctypes.c_uint64(0)
+    rc = _load().orc_symmetric(ptrs, nws.ctypes.data, N, n_bits, tab.ctypes.data, out.ctypes.data, cap,
+                               ctypes.byref(n))
+    if rc != OK:
+        raise OracleError(rc, "symmetric")
+    return out[: n.value].copy()
