@@ -124,6 +124,22 @@ uint64_t ewah_output_bound(uint64_t n_bits, uint64_t sum_input_words);
 ewah_status ewah_threshold(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
                            uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream);
 
+/*
+ * General symmetric function of the N input bits of every row (Section 2: the
+ * threshold functions are a subset of the symmetric Boolean functions, which
+ * include at-most-T and count-in-[T1, T2]; Section 3.2: a symmetric function is
+ * determined by the number of ones among its inputs, XOR being the example;
+ * Section 5.1: a counter-based method takes any function from [0, N] to the
+ * Booleans).  Output row i is f[c_i], where c_i is the number of inputs with
+ * row i set and f[0..n] is a host table (f_len = n + 1 bytes, 0 or non-zero),
+ * read during the call only.  Supported: any f whose counts giving 1 form at
+ * most 8 runs (at least T, at most T, exactly T, ranges, their complements...),
+ * and odd or even parity; any other table is EINVAL.  Inputs, output buffers,
+ * bound, errors and asynchrony as for ewah_threshold.
+ */
+ewah_status ewah_symmetric(const ewah_bitmap* const* in, uint32_t n, const uint8_t* f, uint32_t f_len,
+                           uint64_t* out_words_dev, uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream);
+
 /* As ewah_threshold with an explicit kernel variant (ewah_variant_code); the result is identical. */
 ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
                              uint64_t out_cap, uint64_t* out_n_words_dev, uint32_t variant, void* hip_stream);

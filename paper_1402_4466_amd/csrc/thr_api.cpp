@@ -431,8 +431,15 @@ ewah_status ewah_get_stats(const ewah_bitmap* b, ewah_stats* out) {
 
 const uint64_t* ewah_device_words(const ewah_bitmap* b) { return b ? b->dev.words : nullptr; }
 
-ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
-                             uint64_t out_cap, uint64_t* out_n_words_dev, uint32_t variant, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// One query on the single-query kernel: count >= T, or the predicate pred (host copy,
+// uploaded with the input slots) when it is not null.
+ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, const PredDev* pred,
+                      uint64_t* out_words_dev, uint64_t out_cap, uint64_t* out_n_words_dev, uint32_t variant,
+                      void* hip_stream) {
     ewah_status st = ensure_ready();
     if (st) return st;
     if ((n && !in) || !out_n_words_dev) return fail(EWAH_EINVAL, "null argument");
@@ -456,20 +463,24 @@ ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t 
         return EWAH_OK;
     }
     const uint32_t tiles = (U + TW - 1) / TW;
+    // staging: the n slots, then (8-byte aligned) the predicate record
+    const size_t pred_off = ((size_t)n + 1) & ~(size_t)1;
+    const size_t n_stage = pred ? pred_off + sizeof(PredDev) / 4 : n;
     Ctx* c = nullptr;
     st = get_ctx(s, &c);
     if (st) return st;
-    st = ctx_reserve(*c, s, n, tiles);
+    st = ctx_reserve(*c, s, n_stage, tiles);
     if (st) return st;
     HIPCHK(hipEventSynchronize(c->ev));   // previous upload from the staging buffer is done
     for (uint32_t i = 0; i < n; ++i) c->h_ids[i] = in[i]->slot;
-    HIPCHK(hipMemcpyAsync(c->d_ids, c->h_ids, (size_t)n * 4, hipMemcpyHostToDevice, s));
+    if (pred) std::memcpy(c->h_ids + pred_off, pred, sizeof(PredDev));
+    HIPCHK(hipMemcpyAsync(c->d_ids, c->h_ids, n_stage * 4, hipMemcpyHostToDevice, s));
     HIPCHK(hipEventRecord(c->ev, s));
     if ((++c->epoch & 0xFFFFu) == 0) {   // 16-bit tags wrapped: clear stale states
         HIPCHK(hipMemsetAsync(c->d_state, 0, c->state_cap * sizeof(TileState), s));
         c->epoch = 1;
     }
-    QueryDev q;
+    QueryDev q{};
     q.ids = c->d_ids;
     q.out = out_words_dev;
     q.out_n = out_n_words_dev;
@@ -477,18 +488,76 @@ ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t 
     q.stage = nullptr;             // the single-query kernel writes its output in place
     q.cap = out_cap;
     q.N = n;
-    q.T = T;
+    q.T = pred ? pred->tz : T;
     q.U = U;
     q.tiles = tiles;
     q.tail_bits = (uint32_t)(n_bits % 64);
     q.variant = variant ? variant : ewah_default_variant();
+    q.pd = pred ? (const PredDev*)(c->d_ids + pred_off) : nullptr;
     HIPCHK(launch_query(q, g.d_table, c->d_ticket, c->epoch, g.d_err, s));
     return EWAH_OK;
 }
 
+// Device form of a symmetric function given by its table f[0..n]: the runs of counts
+// giving 1 as intervals (at most MAX_IV), or parity; EINVAL otherwise.
+ewah_status pred_from_table(const uint8_t* f, uint32_t n, PredDev& pd) {
+    pd = PredDev{};
+    uint32_t k = 0;
+    bool fits = true;
+    for (uint32_t c = 0; c <= n; ++c) {
+        if (!f[c] || (c > 0 && f[c - 1])) continue;
+        uint32_t e = c;
+        while (e < n && f[e + 1]) ++e;
+        if (k == (uint32_t)MAX_IV) { fits = false; break; }
+        pd.iv[2 * k] = c;
+        pd.iv[2 * k + 1] = e;
+        ++k;
+    }
+    uint32_t tz = 1;
+    while (tz <= n && (f[tz] != 0) == (f[0] != 0)) ++tz;
+    pd.tz = tz;
+    pd.v0 = f[0] ? 1u : 0u;
+    if (fits) {
+        pd.kind = PRED_INTERVALS;
+        pd.n_iv = k;
+        return EWAH_OK;
+    }
+    bool odd = true, even = true;
+    for (uint32_t c = 0; c <= n; ++c) {
+        odd = odd && ((f[c] != 0) == ((c & 1u) != 0));
+        even = even && ((f[c] != 0) == ((c & 1u) == 0));
+    }
+    if (!odd && !even) return fail(EWAH_EINVAL, "symmetric function with more than " + std::to_string(MAX_IV) +
+                                                    " runs of counts giving 1 that is not parity");
+    pd = PredDev{};
+    pd.kind = odd ? PRED_ODD : PRED_EVEN;
+    pd.tz = 1;
+    pd.v0 = even ? 1u : 0u;
+    return EWAH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
+                             uint64_t out_cap, uint64_t* out_n_words_dev, uint32_t variant, void* hip_stream) {
+    return run_plain(in, n, T, nullptr, out_words_dev, out_cap, out_n_words_dev, variant, hip_stream);
+}
+
 ewah_status ewah_threshold(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
                            uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream) {
-    return ewah_threshold_v(in, n, T, out_words_dev, out_cap, out_n_words_dev, 0, hip_stream);
+    return run_plain(in, n, T, nullptr, out_words_dev, out_cap, out_n_words_dev, 0, hip_stream);
+}
+
+ewah_status ewah_symmetric(const ewah_bitmap* const* in, uint32_t n, const uint8_t* f, uint32_t f_len,
+                           uint64_t* out_words_dev, uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream) {
+    if (!f) return fail(EWAH_EINVAL, "null function table");
+    if (f_len != n + 1) return fail(EWAH_EINVAL, "the function table needs n + 1 entries (counts 0..n)");
+    PredDev pd;
+    ewah_status st = pred_from_table(f, n, pd);
+    if (st) return st;
+    return run_plain(in, n, pd.tz, &pd, out_words_dev, out_cap, out_n_words_dev, 0, hip_stream);
 }
 
 ewah_status ewah_device_errors(uint32_t* flags) {
@@ -624,6 +693,7 @@ ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, con
         d.tiles = tiles;
         d.tail_bits = (uint32_t)(n_bits % 64);
         d.variant = q[i].variant ? q[i].variant : ewah_default_variant();
+        d.pd = nullptr;   // batches hold threshold queries
     }
     HIPCHK(hipMalloc(&b->d_qs, nq * sizeof(QueryDev)));
     HIPCHK(hipMemcpy(b->d_qs, b->h_qs.data(), nq * sizeof(QueryDev), hipMemcpyHostToDevice));

@@ -108,7 +108,26 @@ struct TileState {
                           // bits 16..17 of head[1]: number of heads, at most 2
 };
 
-struct QueryDev {         // 72 bytes
+// Output predicate of a query, a function f of the row count (a symmetric Boolean
+// function of the N input bits, Section 2 and Section 3.2).
+enum : uint32_t {
+    PRED_THRESHOLD = 0,   // count >= T
+    PRED_INTERVALS = 1,   // count in one of the n_iv intervals [iv[2j], iv[2j + 1]]
+    PRED_ODD = 2,         // count odd (XOR of the inputs)
+    PRED_EVEN = 3,        // count even
+};
+constexpr int MAX_IV = 8;
+
+// Predicate of a query other than a plain threshold (device memory).
+struct PredDev {          // 80 bytes
+    uint32_t kind;        // PRED_*
+    uint32_t n_iv;        // PRED_INTERVALS: sorted, disjoint intervals of counts giving 1
+    uint32_t tz;          // every count below tz gives v0
+    uint32_t v0;
+    uint32_t iv[2 * MAX_IV];
+};
+
+struct QueryDev {         // 88 bytes
     const uint32_t* ids;  // N bitmap slots
     uint64_t* out;        // canonical EWAH output (device)
     uint64_t* out_n;      // output length (device)
@@ -118,6 +137,7 @@ struct QueryDev {         // 72 bytes
     uint32_t N, T, U, tiles;
     uint32_t tail_bits;   // n_bits % 64
     uint32_t variant;     // VAR_* flags
+    const PredDev* pd;    // null: count >= T
 };
 
 // Variant flags (kernel strategy knobs; results never depend on them).

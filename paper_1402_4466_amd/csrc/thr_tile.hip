@@ -434,6 +434,49 @@ __device__ __forceinline__ void issue_batch(const uint4* win, uint32_t w0, uint3
     }
 }
 
+// Whether the query's predicate f takes one value v on every count in [lo, hi]
+// (lo <= hi).  For the threshold this is the RBMrg case split (Section 6.4): lo >= T
+// gives all ones, hi < T all zeros.
+__device__ __forceinline__ bool pred_uniform(const QueryDev& q, uint32_t lo, uint32_t hi, uint32_t& v) {
+    const PredDev* pd = q.pd;
+    if (pd == nullptr || pd->kind == PRED_THRESHOLD) {
+        if (lo >= q.T) { v = 1u; return true; }
+        if (hi < q.T) { v = 0u; return true; }
+        return false;
+    }
+    const uint32_t kind = pd->kind;
+    if (kind == PRED_INTERVALS) {
+        // the piece of f that holds lo: a gap before interval j, interval j, or the gap after
+        // the last interval; f is constant on [lo, hi] iff hi stays in that piece
+        uint32_t end = 0xFFFFFFFFu;
+        v = 0u;
+        const uint32_t n_iv = pd->n_iv;
+        for (uint32_t j = 0; j < n_iv; ++j) {
+            const uint32_t a = pd->iv[2 * j], b = pd->iv[2 * j + 1];
+            if (lo < a) { end = a - 1u; break; }
+            if (lo <= b) { v = 1u; end = b; break; }
+        }
+        return hi <= end;
+    }
+    // parity: constant only where every count is the same
+    v = (lo & 1u) ^ (kind == PRED_EVEN ? 1u : 0u);
+    return lo == hi;
+}
+
+// Rows with count >= x, where the count of each of the 64 rows of a word is held
+// bit-sliced in R[0..P-1] (least significant plane first).
+__device__ __forceinline__ uint64_t sliced_ge(const uint64_t* R, int P, int x) {
+    if (x <= 0) return ~0ull;
+    if (x >= (1 << P)) return 0ull;
+    uint64_t gt = 0, eq = ~0ull;
+    for (int p = P - 1; p >= 0; --p) {
+        const uint64_t tb = ((x >> p) & 1) ? ~0ull : 0ull;
+        gt |= eq & R[p] & ~tb;
+        eq &= ~(R[p] ^ tb);
+    }
+    return gt | eq;
+}
+
 // Per-group input counts from presence words staged in LDS word-major (word w of
 // input k at w * pcap + k) for the first ns inputs.  QS lanes share a quad of groups
 // (BLOCK = groups / 4 * QS), each counting every QS-th input.  A lane keeps the four
@@ -471,7 +514,7 @@ static_assert(PCAP_FINE / 4 < 256u && PCAP_COARSE / 16 < 256u, "byte counters");
 // STAGED: the tile writes its words to the staging area and publishes its
 // aggregate (a placement pass finishes the output); otherwise it finds the prefix
 // over earlier tiles by look-back and writes its words in place.
-template <bool STAGED>
+template <bool STAGED, bool GENERAL = false>
 __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ table, uint32_t t,
                              uint32_t epoch, unsigned char* smem, uint32_t* err, uint32_t dbg_slot) {
     (void)dbg_slot;   // timestamp slot of debug builds
@@ -504,7 +547,10 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     __syncthreads();
 
     // ---- classify / prune (RBMrg on EWAH, cases 1 and 2, per tile)
-    const bool trivial = (T == 0) || (T > N);
+    // f constant on every possible count (threshold: T = 0 or T > N)
+    uint32_t tv = T == 0 ? 1u : 0u;
+    bool trivial = (T == 0) || (T > N);
+    if constexpr (GENERAL) trivial = pred_uniform(q, 0u, N, tv);
     Seg seg;
     BitmapDev B0;
     // presence granularity: single words for queries of up to PCAP_FINE inputs, else
@@ -555,8 +601,21 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     }
     __syncthreads();
     EWT_PHASE(1);
-    uint32_t mode = trivial ? (T == 0 ? 1u : 2u)
+    // every row count of the tile lies in [full one-fills, inputs that can hold a one]
+    uint32_t mode = trivial ? (tv ? 1u : 2u)
                             : (misc[M_ONEFULL] >= T ? 1u : (misc[M_NONZERO] < T ? 2u : 0u));
+    if constexpr (GENERAL) {
+        uint32_t uv = 0;
+        if (!trivial) mode = pred_uniform(q, misc[M_ONEFULL], max(misc[M_ONEFULL], misc[M_NONZERO]), uv) ? (uv ? 1u : 2u) : 0u;
+        mode = (uint32_t)__builtin_amdgcn_readfirstlane((int)mode);   // uniform (it depends on LDS counters)
+    }
+    // per-group bounds: a group whose bound is below tz has every count below tz, where
+    // f is v0 (for the threshold: below T, zero)
+    uint32_t Tz = T, v0 = 0;
+    if constexpr (GENERAL) {
+        Tz = (uint32_t)__builtin_amdgcn_readfirstlane((int)q.pd->tz);
+        v0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)q.pd->v0);
+    }
     // per-group bounds: counted only when fewer than T inputs touch every group and
     // T is above 9/10 of the mean bound (else few groups, if any, fall below T)
     PMask pm;
@@ -564,7 +623,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     pm.sh = gsh;
     pm.ng = ng;
     pm.on = false;
-    if (mode == 0 && misc[M_DFULL] < T && 10ull * T * ngv > 9ull * misc[M_PSUM]) {
+    if (mode == 0 && misc[M_DFULL] < Tz && 10ull * Tz * ngv > 9ull * misc[M_PSUM]) {
         if (fine) count_quads<4>(prs, PCAP_FINE, min(N, PCAP_FINE), gcnt);
         else count_quads<16>(prs, PCAP_COARSE, min(N, PCAP_COARSE), gcnt);
         if (N > pcap) {   // the rest of very wide queries (4-word groups): wavefront ballots
@@ -584,7 +643,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         }
         __syncthreads();
         if ((uint32_t)tid < ng) {
-            const uint64_t m = __ballot(gcnt[tid] < T && (uint32_t)tid < ngv);
+            const uint64_t m = __ballot(gcnt[tid] < Tz && (uint32_t)tid < ngv);
             if ((tid & 63) == 0) { misc[M_PR + 2 * (tid >> 6)] = (uint32_t)m; misc[M_PR + 2 * (tid >> 6) + 1] = (uint32_t)(m >> 32); }
         }
         __syncthreads();
@@ -593,7 +652,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         for (int i = 0; i < PMW_MAX; ++i)
             if ((uint32_t)i < ng / 32u) npr += (uint32_t)__popc(misc[M_PR + i]);
         pm.on = npr != 0u;
-        if (npr == ngv) mode = 2u;
+        if (npr == ngv) mode = v0 ? 1u : 2u;
     }
     const bool prune = pm.any();
 
@@ -777,7 +836,8 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     }
 
     EWT_PHASE(4);
-    // ---- compare: count >= T - k1 per row, bit-sliced
+    // ---- compare: f(count) per row, where count = planes + k1 (the one-fills at the
+    // position), bit-sliced; the threshold compares the planes with T - k1
     uint32_t k1tot;
     int32_t dv = tid < TW ? diff[tid] : 0;
     uint32_t k1 = block_excl_scan((uint32_t)dv, misc + M_TMP, k1tot) + (uint32_t)dv;
@@ -785,7 +845,22 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     if ((uint32_t)tid < nPos) {
         if (mode == 1) o = ~0ull;
         else if (mode == 2) o = 0;
-        else {
+        else if (GENERAL && q.pd->kind != PRED_THRESHOLD) {
+            const PredDev* pd = q.pd;
+            uint64_t R[MAXP];
+#pragma unroll
+            for (int p = 0; p < MAXP; ++p) R[p] = p < P ? planes[p * TW + tid] : 0ull;
+            if (pd->kind == PRED_INTERVALS) {
+                // count in [a, b]  <=>  planes in [a - k1, b - k1]
+                const uint32_t n_iv = pd->n_iv;
+                for (uint32_t j = 0; j < n_iv; ++j) {
+                    const int lo = (int)pd->iv[2 * j] - (int)k1, hi = (int)pd->iv[2 * j + 1] - (int)k1;
+                    o |= sliced_ge(R, P, lo) & ~sliced_ge(R, P, hi + 1);
+                }
+            } else {   // parity of planes + k1: plane 0 flipped when k1 is odd
+                o = R[0] ^ (((k1 & 1u) ^ (pd->kind == PRED_EVEN ? 1u : 0u)) ? ~0ull : 0ull);
+            }
+        } else {
             int tp = (int)T - (int)k1;
             if (tp <= 0) o = ~0ull;
             else if (tp >= (1 << P)) o = 0;
@@ -1101,6 +1176,21 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_kernel(QueryDev q, const B
     process_tile<false>(q, table, s_t, epoch, smem, err, s_t);
 }
 
+// The same for a general symmetric predicate (q.pd: intervals of counts or parity),
+// a separate instantiation so that the threshold kernels keep their registers.
+__global__ __launch_bounds__(BLOCK, 4) void thr_query_sym_kernel(QueryDev q, const BitmapDev* __restrict__ table,
+                                                          uint32_t* ticket, uint32_t epoch, uint32_t* err) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_t;
+    if (threadIdx.x == 0) {
+        uint32_t t = atomicAdd(ticket, 1u);
+        if (t == q.tiles - 1) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_t = t;
+    }
+    __syncthreads();
+    process_tile<false, true>(q, table, s_t, epoch, smem, err, s_t);
+}
+
 // Many queries in one persistent launch.  The (query, tile) items are split into
 // NXCD contiguous ranges, one per XCD (workgroup i runs on XCD i mod NXCD), so that
 // neighbouring tiles of a query, which share the compressed chunk at their boundary,
@@ -1186,6 +1276,8 @@ namespace ewt {
 hipError_t set_smem_limits(size_t max_bytes) {
     hipError_t e = hipFuncSetAttribute((const void*)thr_query_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)thr_query_sym_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)thr_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
 }
 
@@ -1198,7 +1290,8 @@ int batch_blocks_per_cu(size_t smem) {
 hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* ticket, uint32_t epoch, uint32_t* err,
                         hipStream_t s) {
     size_t smem = tile_smem_bytes(q.N);
-    hipLaunchKernelGGL(thr_query_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
+    if (q.pd) hipLaunchKernelGGL(thr_query_sym_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
+    else hipLaunchKernelGGL(thr_query_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
     return hipGetLastError();
 }
 

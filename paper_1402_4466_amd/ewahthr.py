@@ -67,6 +67,7 @@ _get_stats = _sig("ewah_get_stats", _i32, [_vp, ctypes.POINTER(Stats)])
 _device_words = _sig("ewah_device_words", _vp, [_vp])
 _output_bound = _sig("ewah_output_bound", _u64, [_u64, _u64])
 _threshold_v = _sig("ewah_threshold_v", _i32, [ctypes.POINTER(_vp), _u32, _u32, _vp, _u64, _vp, _u32, _vp])
+_symmetric = _sig("ewah_symmetric", _i32, [ctypes.POINTER(_vp), _u32, _vp, _u32, _vp, _u64, _vp, _vp])
 _variant_code = _sig("ewah_variant_code", _u32, [_i32, _u32, _u32])
 _default_variant = _sig("ewah_default_variant", _u32, [])
 _batch_plan = _sig("ewah_batch_plan", _i32, [ctypes.POINTER(_vp), _u32, ctypes.POINTER(Query), _u32,
@@ -93,6 +94,7 @@ _mlp_last_error = _sig("ewah_mlp_last_error", ctypes.c_char_p, [])
 
 EXPORTED = ["ewah_init", "ewah_last_error", "ewah_register", "ewah_register_many", "ewah_release",
             "ewah_get_stats", "ewah_device_words", "ewah_output_bound", "ewah_threshold", "ewah_threshold_v",
+            "ewah_symmetric",
             "ewah_variant_code", "ewah_default_variant", "ewah_batch_plan", "ewah_batch_run",
             "ewah_batch_set_variants", "ewah_batch_set_grid", "ewah_batch_free", "ewah_device_errors",
             "ewah_num_cus", "ewah_query_features", "ewah_batch_features", "ewah_batch_select",
@@ -202,6 +204,15 @@ def threshold(bitmaps, T: int, out_words_ptr: int, out_cap: int, out_n_ptr: int,
     n = len(bitmaps)
     arr = (_vp * max(n, 1))(*[b.handle for b in bitmaps])
     _check(_threshold_v(arr, n, T, out_words_ptr, out_cap, out_n_ptr, variant, _stream_ptr(stream)), "threshold")
+
+
+def symmetric(bitmaps, f, out_words_ptr: int, out_cap: int, out_n_ptr: int, stream=None):
+    """Enqueue one query of a symmetric function: output row i is f[c_i], c_i = number of inputs
+    with row i set; f is a sequence of len(bitmaps) + 1 truth values (counts 0..N)."""
+    n = len(bitmaps)
+    arr = (_vp * max(n, 1))(*[b.handle for b in bitmaps])
+    tab = (ctypes.c_uint8 * max(len(f), 1))(*[1 if v else 0 for v in f])
+    _check(_symmetric(arr, n, tab, len(f), out_words_ptr, out_cap, out_n_ptr, _stream_ptr(stream)), "symmetric")
 
 
 class Batch:
