@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c4", choices=["c4", "c2", "c3", "c1"])
+    ap.add_argument("--workload", default="c4", choices=["c4", "c2", "c3", "c1", "sym"])
     ap.add_argument("--pool", type=int, default=10_000)
     ap.add_argument("--queries", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -247,6 +247,63 @@ def bench_single(args, E, torch, which):
             "config": {"workload": w.name, "queries": rows, "input_bytes": in_bytes, "copies_rotated": copies}}
 
 
+def bench_sym(args, E, torch):
+    """Symmetric functions of the row count (plain path) on the config-2 inputs: at most one
+    input set, a count in [2, 8], and odd parity (XOR).  Input copies rotated as for config 2."""
+    import time
+    from oracle import oracle as O
+    from paper_1402_4466_amd import datagen as D
+    w = D.config2()
+    n_bits, n = w.n_bits, len(w.streams)
+    in_bytes = sum(len(s) for s in w.streams) * 8
+    copies = max(1, min(8, int(np.ceil(1.2e9 / max(in_bytes, 1)))))
+    sets = [E.register_many(w.streams, n_bits) for _ in range(copies)]
+    stream = torch.cuda.current_stream()
+    tables = {"at_most_1": [1 if c <= 1 else 0 for c in range(n + 1)],
+              "count_in_2_8": [1 if 2 <= c <= 8 else 0 for c in range(n + 1)],
+              "odd_parity": [c % 2 for c in range(n + 1)]}
+    rows, tot_ms, tot_alg = [], 0.0, 0
+    for name, f in tables.items():
+        cap = E.output_bound(n_bits, in_bytes // 8)
+        out = torch.zeros(cap, dtype=torch.int64, device="cuda")
+        out_n = torch.zeros(1, dtype=torch.int64, device="cuda")
+        k = [0]
+
+        def run():
+            bm = sets[k[0] % copies]
+            k[0] += 1
+            E.symmetric(bm, f, out.data_ptr(), cap, out_n.data_ptr(), stream=stream)
+        for _ in range(args.warmup + 1):
+            run()
+        ms = events_time(run, stream, max(args.steps, 10))
+        n_out = int(out_n.item())
+        gbs = in_bytes / (ms / 1e3) / 1e9
+        rows.append({"f": name, "ms": round(ms, 4), "GB/s": round(gbs, 1), "out_words": n_out})
+        tot_ms += ms
+        tot_alg += in_bytes + 8 * n_out
+        log(f"sym {name}: {ms:.4f} ms, {gbs:.1f} GB/s, {n_out} output words")
+    assert E.device_errors() == 0
+    value = len(tables) * in_bytes / (tot_ms / 1e3) / 1e9
+    achieved = tot_alg / (tot_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "thr_query_sym_kernel",
+            "timing": "per call, HIP events on the query stream"}
+    cpu = None
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        O.symmetric(w.streams, n_bits, tables["count_in_2_8"])
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(in_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"one query (count in [2, 8]) over the {n} inputs, {in_bytes / 1e6:.1f} MB, {dt:.2f} s"}
+    return {"metric": "compressed input GB/s for symmetric functions of the count (plain path)", "value": round(value, 2),
+            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(tot_ms / len(tables), 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"sym: {w.name}, f in {list(tables)}", "queries": rows, "input_bytes": in_bytes,
+                       "copies_rotated": copies},
+            "roofline": roof, "cpu_baseline": cpu}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -258,6 +315,8 @@ def main():
     E.init(0)
     if args.workload == "c4":
         res = bench_c4(args, E, torch)
+    elif args.workload == "sym":
+        res = bench_sym(args, E, torch)
     else:
         res = bench_single(args, E, torch, args.workload)
     print(json.dumps(res), flush=True)
