@@ -12,6 +12,8 @@ Functions follow the paper's definitions:
                 histogram
   symmetric  -- the same counting with any function of the count (Sections 2,
                 3.2 and 5.1), returns the canonical EWAH result
+  opt_threshold -- largest T whose result has at least K rows (Section 3.3),
+                read off the count histogram, and that result
 """
 from __future__ import annotations
 
@@ -128,3 +130,22 @@ def symmetric(streams, n_bits: int, f):
     if rc != OK:
         raise OracleError(rc, "symmetric")
     return out[: n.value].copy()
+
+
+def opt_threshold(streams, n_bits: int, K: int):
+    """(T, canonical EWAH words of the T-of-N result) for the largest T in [0, N] whose result has at
+    least K rows (Section 3.3; K = 1 is the largest row count, as ScanCount reads it off its
+    counters, Section 5.1).  The row counts come from the count histogram h: |result(T)| is the sum
+    of h[c] over c >= T."""
+    N = len(streams)
+    if not 1 <= K <= n_bits:
+        raise ValueError("K must be in [1, n_bits]")
+    _, hist = threshold(streams, n_bits, N + 1, want_hist=True)
+    best, above = 0, 0
+    for T in range(N, -1, -1):
+        above += int(hist[T])
+        if above >= K:
+            best = T
+            break
+    out, _ = threshold(streams, n_bits, best, want_hist=False)
+    return best, out
