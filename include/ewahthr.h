@@ -140,6 +140,21 @@ ewah_status ewah_threshold(const ewah_bitmap* const* in, uint32_t n, uint32_t T,
 ewah_status ewah_symmetric(const ewah_bitmap* const* in, uint32_t n, const uint8_t* f, uint32_t f_len,
                            uint64_t* out_words_dev, uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream);
 
+/*
+ * Opt-threshold query (Section 3.3): T is not given; the query takes the
+ * largest T in [0, n] whose T-of-N result has at least K rows (K = 1: the
+ * largest T with a non-empty result, which is the largest row count, as
+ * ScanCount finds it from its counters, Section 5.1) and returns that result.
+ * *T_out (host memory) receives T; output buffers, bound and errors as for
+ * ewah_threshold.  1 <= K <= n_bits, else EINVAL.  One pass over the inputs
+ * finds the largest count (tiles that cannot exceed the largest count seen so
+ * far are skipped); K > 1 adds a binary search over T with one counting pass
+ * per step.  The call is synchronous: it returns once T is known and the
+ * result has been enqueued on hip_stream.
+ */
+ewah_status ewah_opt_threshold(const ewah_bitmap* const* in, uint32_t n, uint64_t K, uint64_t* out_words_dev,
+                               uint64_t out_cap, uint64_t* out_n_words_dev, uint32_t* T_out, void* hip_stream);
+
 /* As ewah_threshold with an explicit kernel variant (ewah_variant_code); the result is identical. */
 ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
                              uint64_t out_cap, uint64_t* out_n_words_dev, uint32_t variant, void* hip_stream);

@@ -57,6 +57,8 @@ struct Ctx {                       // per-stream query state
     uint32_t* d_ticket = nullptr;  // tile order of the single-query kernel
     uint32_t epoch = 0;
     hipEvent_t ev = nullptr;       // staging buffer free once this completes
+    unsigned long long* d_acc = nullptr;   // opt-threshold: largest count / output row count
+    unsigned long long* h_acc = nullptr;   // pinned copy
 };
 
 struct Lib {
@@ -494,7 +496,28 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
     q.tail_bits = (uint32_t)(n_bits % 64);
     q.variant = variant ? variant : ewah_default_variant();
     q.pd = pred ? (const PredDev*)(c->d_ids + pred_off) : nullptr;
-    HIPCHK(launch_query(q, g.d_table, c->d_ticket, c->epoch, g.d_err, s));
+    HIPCHK(launch_query(q, g.d_table, c->d_ticket, c->epoch, g.d_err, s, pred ? pred->kind : (uint32_t)PRED_THRESHOLD));
+    return EWAH_OK;
+}
+
+// Runs one query whose predicate record accumulates into the stream's accumulator
+// and returns the accumulated value (synchronous).
+ewah_status run_accumulate(const ewah_bitmap* const* in, uint32_t n, PredDev& pd, uint64_t* out_words_dev,
+                           uint64_t out_cap, uint64_t* out_n_words_dev, hipStream_t s, uint64_t& value) {
+    Ctx* c = nullptr;
+    ewah_status st = get_ctx(s, &c);
+    if (st) return st;
+    if (!c->d_acc) {
+        HIPCHK(hipMalloc(&c->d_acc, 16));
+        HIPCHK(hipHostMalloc(&c->h_acc, 16, hipHostMallocDefault));
+    }
+    HIPCHK(hipMemsetAsync(c->d_acc, 0, 8, s));
+    pd.acc = c->d_acc;
+    st = run_plain(in, n, pd.tz, &pd, out_words_dev, out_cap, out_n_words_dev, 0, s);
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(c->h_acc, c->d_acc, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    value = *c->h_acc;
     return EWAH_OK;
 }
 
@@ -548,6 +571,39 @@ ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t 
 ewah_status ewah_threshold(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
                            uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream) {
     return run_plain(in, n, T, nullptr, out_words_dev, out_cap, out_n_words_dev, 0, hip_stream);
+}
+
+ewah_status ewah_opt_threshold(const ewah_bitmap* const* in, uint32_t n, uint64_t K, uint64_t* out_words_dev,
+                               uint64_t out_cap, uint64_t* out_n_words_dev, uint32_t* T_out, void* hip_stream) {
+    if (!T_out) return fail(EWAH_EINVAL, "null T_out");
+    if (n && in && in[0] && (K == 0 || K > in[0]->stats.n_bits))
+        return fail(EWAH_EINVAL, "K must be in [1, n_bits]");
+    hipStream_t s = (hipStream_t)hip_stream;
+    // the largest row count M (one pass, branch and bound over the tiles)
+    PredDev pd{};
+    pd.kind = PRED_MAXCOUNT;
+    pd.tz = 1;
+    uint64_t M = 0;
+    ewah_status st = run_accumulate(in, n, pd, out_words_dev, out_cap, out_n_words_dev, s, M);
+    if (st) return st;
+    uint32_t best = (uint32_t)M;   // K = 1: the rows of count M exist (T = 0 if no row is set)
+    if (K > 1 && M > 0) {
+        // largest T in [0, M] whose result has at least K rows; T = 0 gives all n_bits >= K rows
+        uint32_t lo = 0, hi = (uint32_t)M;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) / 2;
+            PredDev tp{};
+            tp.kind = PRED_THRESHOLD;
+            tp.tz = mid;
+            uint64_t rows = 0;
+            st = run_accumulate(in, n, tp, out_words_dev, out_cap, out_n_words_dev, s, rows);
+            if (st) return st;
+            if (rows >= K) lo = mid; else hi = mid - 1;
+        }
+        best = lo;
+    }
+    *T_out = best;
+    return run_plain(in, n, best, nullptr, out_words_dev, out_cap, out_n_words_dev, 0, hip_stream);
 }
 
 ewah_status ewah_symmetric(const ewah_bitmap* const* in, uint32_t n, const uint8_t* f, uint32_t f_len,

@@ -115,16 +115,19 @@ enum : uint32_t {
     PRED_INTERVALS = 1,   // count in one of the n_iv intervals [iv[2j], iv[2j + 1]]
     PRED_ODD = 2,         // count odd (XOR of the inputs)
     PRED_EVEN = 3,        // count even
+    PRED_MAXCOUNT = 4,    // no output: the largest row count goes to *acc (atomic maximum)
 };
 constexpr int MAX_IV = 8;
 
 // Predicate of a query other than a plain threshold (device memory).
-struct PredDev {          // 80 bytes
+struct PredDev {          // 88 bytes
     uint32_t kind;        // PRED_*
     uint32_t n_iv;        // PRED_INTERVALS: sorted, disjoint intervals of counts giving 1
     uint32_t tz;          // every count below tz gives v0
     uint32_t v0;
     uint32_t iv[2 * MAX_IV];
+    unsigned long long* acc;   // PRED_MAXCOUNT: running maximum; else, if not null, receives
+                               // the number of output rows (added)
 };
 
 struct QueryDev {         // 88 bytes
@@ -182,7 +185,7 @@ __host__ __device__ inline size_t tile_smem_bytes(uint32_t N) {
 
 // Host-side launchers (defined with the kernels).
 hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* ticket, uint32_t epoch, uint32_t* err,
-                        hipStream_t s);
+                        hipStream_t s, uint32_t pred_kind = PRED_THRESHOLD);   // kind of *q.pd
 hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_t* tq, uint32_t nq, uint32_t total,
                         const BitmapDev* table, uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid,
                         size_t smem, hipStream_t s);

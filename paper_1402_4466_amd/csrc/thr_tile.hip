@@ -341,7 +341,7 @@ __device__ uint64_t* ewt_phase_buf;
 #endif
 
 // Misc LDS slots.
-enum { M_NDENSE = 1, M_PSUM = 2, M_ONEFULL = 4, M_NONZERO = 5, M_DFULL = 6, M_TMP = 8, M_X = 32, M_TOT = 40, M_PR = 64 };
+enum { M_NDENSE = 1, M_PSUM = 2, M_ONEFULL = 4, M_NONZERO = 5, M_DFULL = 6, M_MAX = 7, M_TMP = 8, M_X = 32, M_TOT = 40, M_PR = 64 };
 static_assert(M_PR + PMW_MAX <= MISC_WORDS, "misc slots");
 
 // Presence group of tile-relative position rel is pruned (positions outside the
@@ -514,7 +514,7 @@ static_assert(PCAP_FINE / 4 < 256u && PCAP_COARSE / 16 < 256u, "byte counters");
 // STAGED: the tile writes its words to the staging area and publishes its
 // aggregate (a placement pass finishes the output); otherwise it finds the prefix
 // over earlier tiles by look-back and writes its words in place.
-template <bool STAGED, bool GENERAL = false>
+template <bool STAGED, bool GENERAL = false, bool MAXC = false>
 __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ table, uint32_t t,
                              uint32_t epoch, unsigned char* smem, uint32_t* err, uint32_t dbg_slot) {
     (void)dbg_slot;   // timestamp slot of debug builds
@@ -551,6 +551,14 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     uint32_t tv = T == 0 ? 1u : 0u;
     bool trivial = (T == 0) || (T > N);
     if constexpr (GENERAL) trivial = pred_uniform(q, 0u, N, tv);
+    // largest count: the running maximum over the tiles done so far bounds what is
+    // worth counting (branch and bound); no tile is trivial
+    uint32_t Rmax = 0;
+    if constexpr (MAXC) {
+        trivial = false;
+        Rmax = (uint32_t)__builtin_amdgcn_readfirstlane(
+            (int)(uint32_t)__hip_atomic_load(q.pd->acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
     Seg seg;
     BitmapDev B0;
     // presence granularity: single words for queries of up to PCAP_FINE inputs, else
@@ -615,6 +623,18 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     if constexpr (GENERAL) {
         Tz = (uint32_t)__builtin_amdgcn_readfirstlane((int)q.pd->tz);
         v0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)q.pd->v0);
+    }
+    if constexpr (MAXC) {
+        // every count of the tile is at most the number of inputs that can hold a one
+        // there; if those are all full one-fills, every count equals it
+        const uint32_t lo = misc[M_ONEFULL], hi = misc[M_NONZERO];
+        if (hi <= Rmax) return;
+        if (lo >= hi) {
+            if (tid == 0) atomicMax(q.pd->acc, (unsigned long long)hi);
+            return;
+        }
+        mode = 0u;
+        Tz = Rmax + 1u;   // groups that cannot exceed the running maximum add nothing
     }
     // per-group bounds: counted only when fewer than T inputs touch every group and
     // T is above 9/10 of the mean bound (else few groups, if any, fall below T)
@@ -841,6 +861,22 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     uint32_t k1tot;
     int32_t dv = tid < TW ? diff[tid] : 0;
     uint32_t k1 = block_excl_scan((uint32_t)dv, misc + M_TMP, k1tot) + (uint32_t)dv;
+    if constexpr (MAXC) {
+        // largest planes value over the word's valid rows (bit-sliced maximum: keep the
+        // rows holding the highest plane bit seen so far), plus the position's one-fills
+        if ((uint32_t)tid < nPos) {
+            uint64_t cand = (tS + (uint32_t)tid == U - 1u && q.tail_bits) ? ((1ull << q.tail_bits) - 1ull) : ~0ull;
+            uint32_t m = 0;
+            for (int p = P - 1; p >= 0; --p) {
+                const uint64_t tb = cand & planes[p * TW + tid];
+                if (tb) { cand = tb; m |= 1u << p; }
+            }
+            atomicMax(&misc[M_MAX], m + k1);
+        }
+        __syncthreads();
+        if (tid == 0) atomicMax(q.pd->acc, (unsigned long long)misc[M_MAX]);
+        return;
+    }
     uint64_t o = 0;
     if ((uint32_t)tid < nPos) {
         if (mode == 1) o = ~0ull;
@@ -876,6 +912,15 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             }
         }
         if (tS + (uint32_t)tid == U - 1u && q.tail_bits) o &= (1ull << q.tail_bits) - 1ull;
+    }
+    if constexpr (GENERAL) {
+        // output row count (one atomic per wavefront), for callers that need |result|
+        const uint64_t accp = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)q.pd->acc >> 32)) << 32) |
+                              (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uint64_t)q.pd->acc);
+        if (accp) {
+            const uint32_t c = wave_incl_scan((uint32_t)__popcll(o));
+            if (lane == 63 && c) atomicAdd((unsigned long long*)accp, (unsigned long long)c);
+        }
     }
     __syncthreads();   // planes are reused below
     EWT_PHASE(5);
@@ -1191,6 +1236,20 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_sym_kernel(QueryDev q, con
     process_tile<false, true>(q, table, s_t, epoch, smem, err, s_t);
 }
 
+// Largest row count of a query (q.pd->kind = PRED_MAXCOUNT): no output is written.
+__global__ __launch_bounds__(BLOCK, 4) void thr_query_max_kernel(QueryDev q, const BitmapDev* __restrict__ table,
+                                                          uint32_t* ticket, uint32_t epoch, uint32_t* err) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_t;
+    if (threadIdx.x == 0) {
+        uint32_t t = atomicAdd(ticket, 1u);
+        if (t == q.tiles - 1) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_t = t;
+    }
+    __syncthreads();
+    process_tile<false, false, true>(q, table, s_t, epoch, smem, err, s_t);
+}
+
 // Many queries in one persistent launch.  The (query, tile) items are split into
 // NXCD contiguous ranges, one per XCD (workgroup i runs on XCD i mod NXCD), so that
 // neighbouring tiles of a query, which share the compressed chunk at their boundary,
@@ -1278,6 +1337,8 @@ hipError_t set_smem_limits(size_t max_bytes) {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void*)thr_query_sym_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)thr_query_max_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)thr_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
 }
 
@@ -1288,10 +1349,12 @@ int batch_blocks_per_cu(size_t smem) {
 }
 
 hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* ticket, uint32_t epoch, uint32_t* err,
-                        hipStream_t s) {
+                        hipStream_t s, uint32_t pred_kind) {
     size_t smem = tile_smem_bytes(q.N);
-    if (q.pd) hipLaunchKernelGGL(thr_query_sym_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
-    else hipLaunchKernelGGL(thr_query_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
+    if (!q.pd) hipLaunchKernelGGL(thr_query_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
+    else if (pred_kind == PRED_MAXCOUNT)
+        hipLaunchKernelGGL(thr_query_max_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
+    else hipLaunchKernelGGL(thr_query_sym_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
     return hipGetLastError();
 }
 

@@ -68,6 +68,8 @@ _device_words = _sig("ewah_device_words", _vp, [_vp])
 _output_bound = _sig("ewah_output_bound", _u64, [_u64, _u64])
 _threshold_v = _sig("ewah_threshold_v", _i32, [ctypes.POINTER(_vp), _u32, _u32, _vp, _u64, _vp, _u32, _vp])
 _symmetric = _sig("ewah_symmetric", _i32, [ctypes.POINTER(_vp), _u32, _vp, _u32, _vp, _u64, _vp, _vp])
+_opt_threshold = _sig("ewah_opt_threshold", _i32, [ctypes.POINTER(_vp), _u32, _u64, _vp, _u64, _vp,
+                                                   ctypes.POINTER(_u32), _vp])
 _variant_code = _sig("ewah_variant_code", _u32, [_i32, _u32, _u32])
 _default_variant = _sig("ewah_default_variant", _u32, [])
 _batch_plan = _sig("ewah_batch_plan", _i32, [ctypes.POINTER(_vp), _u32, ctypes.POINTER(Query), _u32,
@@ -94,7 +96,7 @@ _mlp_last_error = _sig("ewah_mlp_last_error", ctypes.c_char_p, [])
 
 EXPORTED = ["ewah_init", "ewah_last_error", "ewah_register", "ewah_register_many", "ewah_release",
             "ewah_get_stats", "ewah_device_words", "ewah_output_bound", "ewah_threshold", "ewah_threshold_v",
-            "ewah_symmetric",
+            "ewah_symmetric", "ewah_opt_threshold",
             "ewah_variant_code", "ewah_default_variant", "ewah_batch_plan", "ewah_batch_run",
             "ewah_batch_set_variants", "ewah_batch_set_grid", "ewah_batch_free", "ewah_device_errors",
             "ewah_num_cus", "ewah_query_features", "ewah_batch_features", "ewah_batch_select",
@@ -213,6 +215,17 @@ def symmetric(bitmaps, f, out_words_ptr: int, out_cap: int, out_n_ptr: int, stre
     arr = (_vp * max(n, 1))(*[b.handle for b in bitmaps])
     tab = (ctypes.c_uint8 * max(len(f), 1))(*[1 if v else 0 for v in f])
     _check(_symmetric(arr, n, tab, len(f), out_words_ptr, out_cap, out_n_ptr, _stream_ptr(stream)), "symmetric")
+
+
+def opt_threshold(bitmaps, K: int, out_words_ptr: int, out_cap: int, out_n_ptr: int, stream=None) -> int:
+    """Largest T whose T-of-N result has at least K rows; its result is enqueued to the outputs.
+    Returns T (the call waits for it)."""
+    n = len(bitmaps)
+    arr = (_vp * max(n, 1))(*[b.handle for b in bitmaps])
+    t = _u32(0)
+    _check(_opt_threshold(arr, n, K, out_words_ptr, out_cap, out_n_ptr, ctypes.byref(t), _stream_ptr(stream)),
+           "opt_threshold")
+    return int(t.value)
 
 
 class Batch:
