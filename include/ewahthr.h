@@ -166,6 +166,15 @@ ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t 
  * before it is split across a wavefront.
  */
 uint32_t ewah_variant_code(int dense, uint32_t walk, uint32_t litwalk);
+/*
+ * As ewah_variant_code, plus the per-row counter.  looped = 0: bit-sliced binary
+ * counter with ripple-carry adds (the accumulator of BSTM, Section 5.3.1; with
+ * dense = 1, whole-tile dirty runs go through a carry-save-adder tree instead);
+ * looped = 1: unary saturating counter, one level per count 1..T (the Looped
+ * recurrence, Section 6.2), taken when T <= bit length of N, else the binary
+ * counter runs; dense is then ignored.  The result never depends on the code.
+ */
+uint32_t ewah_variant_code_ex(int dense, uint32_t walk, uint32_t litwalk, int looped);
 uint32_t ewah_default_variant(void);
 
 /* ------------------------------------------------------------ batched path */

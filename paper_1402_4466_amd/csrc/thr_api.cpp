@@ -318,6 +318,9 @@ uint64_t ewah_output_bound(uint64_t n_bits, uint64_t sum_input_words) {
 }
 
 uint32_t ewah_variant_code(int dense, uint32_t walk, uint32_t litwalk) { return var_make(dense != 0, walk, litwalk); }
+uint32_t ewah_variant_code_ex(int dense, uint32_t walk, uint32_t litwalk, int looped) {
+    return var_make(dense != 0, walk, litwalk, looped != 0);
+}
 uint32_t ewah_default_variant(void) { return var_make(true, 8, 8); }
 
 ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device, ewah_bitmap** out) {

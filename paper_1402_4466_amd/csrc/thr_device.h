@@ -148,18 +148,25 @@ enum : uint32_t {
     VAR_DENSE = 1u << 0,        // whole-tile dirty runs through the register CSA tree
     VAR_WALK_SHIFT = 8,         // bits 8..15: max compressed words for a one-lane walk
     VAR_LITWALK_SHIFT = 16,     // bits 16..23: max literal-block words for a one-lane loop
+    VAR_LOOPED = 1u << 24,      // unary (saturating) per-row counter, for T <= planes_for(N)
     VAR_EXPLICIT = 1u << 31,    // set in every explicit code so that 0 can mean "default"
 };
 
-__host__ __device__ inline uint32_t var_make(bool dense, uint32_t walk, uint32_t litwalk) {
+__host__ __device__ inline uint32_t var_make(bool dense, uint32_t walk, uint32_t litwalk, bool looped = false) {
     return VAR_EXPLICIT | (dense ? VAR_DENSE : 0u) | ((walk & 255u) << VAR_WALK_SHIFT) |
-           ((litwalk & 255u) << VAR_LITWALK_SHIFT);
+           ((litwalk & 255u) << VAR_LITWALK_SHIFT) | (looped ? VAR_LOOPED : 0u);
 }
 
 __host__ __device__ inline int planes_for(uint32_t n) {
     int p = 1;
     while (p < MAXP && (n >> p) != 0) ++p;
     return p;
+}
+
+// The unary counter keeps one level per count 1..T in the planes' storage, so it
+// applies when T fits there; otherwise the binary counter runs (same result).
+__host__ __device__ inline bool use_looped(uint32_t variant, uint32_t N, uint32_t T) {
+    return (variant & VAR_LOOPED) && T >= 1u && (int)T <= planes_for(N);
 }
 
 constexpr int WCAP = 2 * BLOCK;   // cooperative windows listed in LDS per round

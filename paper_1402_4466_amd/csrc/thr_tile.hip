@@ -74,9 +74,22 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, u
 // plane p holds bit p of every row's count.  Each atomic XOR returns the plane's
 // previous value, whose AND with the incoming bits is the carry into plane p + 1;
 // concurrent adds to one position serialise per plane, so the counts stay exact.
+//
+// Unary counter (LOOPED, the per-word form of the Looped recurrence, Section 6.2):
+// level j holds the rows whose count has reached j + 1, for j < T.  An atomic OR
+// into level j returns its previous value; the rows already there pass on to level
+// j + 1 (a count that reaches T stays there).  The final levels do not depend on the
+// order of the adds, so concurrent adds need no other ordering.
+template <bool LOOPED>
+__device__ __forceinline__ uint64_t plane_add(uint64_t* planes, uint32_t p, uint32_t pos, uint64_t v) {
+    if constexpr (LOOPED) return atomicOr((unsigned long long*)&planes[p * TW + pos], (unsigned long long)v);
+    else return atomicXor((unsigned long long*)&planes[p * TW + pos], (unsigned long long)v);
+}
+
+template <bool LOOPED>
 __device__ __forceinline__ void ripple_add(uint64_t* planes, uint32_t pos, uint64_t v, int P) {
     for (int p = 0; p < P && v; ++p) {
-        uint64_t old = atomicXor((unsigned long long*)&planes[p * TW + pos], (unsigned long long)v);
+        uint64_t old = plane_add<LOOPED>(planes, (uint32_t)p, pos, v);
         v &= old;
     }
 }
@@ -192,6 +205,7 @@ __device__ __forceinline__ bool pruned_at(const PMask& pm, uint32_t rel);
 // starts at y0) and adds whatever falls inside [tS, tE).  Words are read eight
 // at a time; streams are padded so reads up to CHUNK words past the end stay
 // inside the allocation.
+template <bool LOOPED>
 __device__ __forceinline__ void walk_lane(const EWT_GLOBAL uint64_t* words, uint32_t bs, uint32_t be, uint32_t y0,
                                           uint32_t tS, uint32_t tE, uint64_t* planes, int32_t* diff, int P,
                                           const PMask& pm) {
@@ -219,7 +233,7 @@ __device__ __forceinline__ void walk_lane(const EWT_GLOBAL uint64_t* words, uint
                     u += L + K;
                 } else {
                     const uint32_t pos = lb + j;
-                    if (pos >= tS && pos < tE && !(prune && pruned_at(pm, pos - tS))) ripple_add(planes, pos - tS, w[i], P);
+                    if (pos >= tS && pos < tE && !(prune && pruned_at(pm, pos - tS))) ripple_add<LOOPED>(planes, pos - tS, w[i], P);
                 }
             }
         }
@@ -228,6 +242,7 @@ __device__ __forceinline__ void walk_lane(const EWT_GLOBAL uint64_t* words, uint
 
 // One lane adds cnt consecutive dirty words starting at compressed index a,
 // the first at tile-relative position p0.
+template <bool LOOPED>
 __device__ __forceinline__ void lit_lane(const EWT_GLOBAL uint64_t* words, uint32_t a, uint32_t cnt, uint32_t p0,
                                          uint64_t* planes, int P, const PMask& pm) {
     const bool prune = pm.any();
@@ -238,7 +253,7 @@ __device__ __forceinline__ void lit_lane(const EWT_GLOBAL uint64_t* words, uint3
 #pragma unroll
         for (int i = 0; i < 8; ++i)
             if (g0 + (uint32_t)i < cnt && !(prune && pruned_at(pm, p0 + g0 + (uint32_t)i)))
-                ripple_add(planes, p0 + g0 + (uint32_t)i, w[i], P);
+                ripple_add<LOOPED>(planes, p0 + g0 + (uint32_t)i, w[i], P);
     }
 }
 
@@ -514,7 +529,7 @@ static_assert(PCAP_FINE / 4 < 256u && PCAP_COARSE / 16 < 256u, "byte counters");
 // STAGED: the tile writes its words to the staging area and publishes its
 // aggregate (a placement pass finishes the output); otherwise it finds the prefix
 // over earlier tiles by look-back and writes its words in place.
-template <bool STAGED, bool GENERAL = false, bool MAXC = false>
+template <bool STAGED, bool GENERAL = false, bool MAXC = false, bool LOOPED = false>
 __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ table, uint32_t t,
                              uint32_t epoch, unsigned char* smem, uint32_t* err, uint32_t dbg_slot) {
     (void)dbg_slot;   // timestamp slot of debug builds
@@ -525,6 +540,8 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     const uint32_t nPos = min((uint32_t)TW, U - tS);
     const uint32_t tE = tS + nPos;
     const int P = planes_for(N);
+    // levels the adds ripple through: bit planes, or count levels 1..T (unary; T <= P)
+    const int PL = LOOPED ? (int)T : P;
     const uint32_t walk_max = (q.variant >> VAR_WALK_SHIFT) & 255u;
     const uint32_t litwalk_max = (q.variant >> VAR_LITWALK_SHIFT) & 255u;
 
@@ -692,17 +709,17 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                 dp = B.desc;
                 if (s.fa < s.fb) { atomicAdd(&diff[s.fa - tS], 1); atomicAdd(&diff[s.fb - tS], -1); }
                 if (s.cnt) {
-                    if ((q.variant & VAR_DENSE) && s.cnt == nPos) {
+                    if (!LOOPED && (q.variant & VAR_DENSE) && s.cnt == nPos) {
                         uint32_t j = atomicAdd(&misc[M_NDENSE], 1u);
                         dense[j] = wp + s.a_lit;
                     } else if (s.cnt <= litwalk_max) {
-                        lit_lane(gp(wp), s.a_lit, s.cnt, s.la - tS, planes, P, pm);
+                        lit_lane<LOOPED>(gp(wp), s.a_lit, s.cnt, s.la - tS, planes, PL, pm);
                     } else {
                         nlw = (s.cnt + 63u) / 64u;
                     }
                 }
                 if (s.be > s.bs) {
-                    if (s.be - s.bs <= walk_max) walk_lane(gp(wp), s.bs, s.be, s.y0, tS, tE, planes, diff, P, pm);
+                    if (s.be - s.bs <= walk_max) walk_lane<LOOPED>(gp(wp), s.bs, s.be, s.y0, tS, tE, planes, diff, PL, pm);
                     else nww = (s.be - 1u) / 64u - s.bs / 64u + 1u;
                 }
             }
@@ -784,11 +801,11 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                     // of a plane are issued before any result is used, and the batch leaves
                     // once no lane carries (no per-window bookkeeping)
                     if (act) {
-                        for (int p = 0; p < P; ++p) {
+                        for (int p = 0; p < PL; ++p) {
                             uint64_t old[WIN_BATCH];
 #pragma unroll
                             for (int g = 0; g < WIN_BATCH; ++g) {
-                                old[g] = atomicXor((unsigned long long*)&planes[p * TW + r[g]], (unsigned long long)x[g]);
+                                old[g] = plane_add<LOOPED>(planes, (uint32_t)p, r[g], x[g]);
                             }
                             // one wait for all of them (lgkmcnt(0)); without it the compiler cannot
                             // tell that no result is still in flight and waits per atomic
@@ -808,7 +825,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
 
             EWT_PHASE(3);
             // dense rows: Harley-Seal carry-save-adder tree, one lane per word position
-            const uint32_t n_dense = misc[M_NDENSE];
+            const uint32_t n_dense = LOOPED ? 0u : misc[M_NDENSE];   // the unary counter takes no dense rows
             if (n_dense && (uint32_t)tid < nPos && !(prune && pruned_at(pm, (uint32_t)tid))) {
                 uint64_t R[MAXP];
 #pragma unroll
@@ -896,6 +913,10 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             } else {   // parity of planes + k1: plane 0 flipped when k1 is odd
                 o = R[0] ^ (((k1 & 1u) ^ (pd->kind == PRED_EVEN ? 1u : 0u)) ? ~0ull : 0ull);
             }
+        } else if constexpr (LOOPED) {
+            // count >= T  <=>  the literal adds reached level T - k1
+            const int tp = (int)T - (int)k1;
+            o = tp <= 0 ? ~0ull : planes[(tp - 1) * TW + tid];
         } else {
             int tp = (int)T - (int)k1;
             if (tp <= 0) o = ~0ull;
@@ -1221,6 +1242,20 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_kernel(QueryDev q, const B
     process_tile<false>(q, table, s_t, epoch, smem, err, s_t);
 }
 
+// The same with the unary per-row counter (use_looped(q.variant, q.N, q.T) holds).
+__global__ __launch_bounds__(BLOCK, 4) void thr_query_looped_kernel(QueryDev q, const BitmapDev* __restrict__ table,
+                                                                 uint32_t* ticket, uint32_t epoch, uint32_t* err) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_t;
+    if (threadIdx.x == 0) {
+        uint32_t t = atomicAdd(ticket, 1u);
+        if (t == q.tiles - 1) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_t = t;
+    }
+    __syncthreads();
+    process_tile<false, false, false, true>(q, table, s_t, epoch, smem, err, s_t);
+}
+
 // The same for a general symmetric predicate (q.pd: intervals of counts or parity),
 // a separate instantiation so that the threshold kernels keep their registers.
 __global__ __launch_bounds__(BLOCK, 4) void thr_query_sym_kernel(QueryDev q, const BitmapDev* __restrict__ table,
@@ -1293,7 +1328,8 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __r
         const uint32_t qi = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_q);
         if (it >= total) break;
         QueryDev q = qs[qi];
-        process_tile<true>(q, table, it - qtile[qi], epoch, smem, err, it);
+        if (use_looped(q.variant, q.N, q.T)) process_tile<true, false, false, true>(q, table, it - qtile[qi], epoch, smem, err, it);
+        else process_tile<true>(q, table, it - qtile[qi], epoch, smem, err, it);
     }
 }
 
@@ -1339,6 +1375,8 @@ hipError_t set_smem_limits(size_t max_bytes) {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void*)thr_query_max_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)thr_query_looped_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)thr_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
 }
 
@@ -1351,7 +1389,9 @@ int batch_blocks_per_cu(size_t smem) {
 hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* ticket, uint32_t epoch, uint32_t* err,
                         hipStream_t s, uint32_t pred_kind) {
     size_t smem = tile_smem_bytes(q.N);
-    if (!q.pd) hipLaunchKernelGGL(thr_query_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
+    if (!q.pd && use_looped(q.variant, q.N, q.T))
+        hipLaunchKernelGGL(thr_query_looped_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
+    else if (!q.pd) hipLaunchKernelGGL(thr_query_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
     else if (pred_kind == PRED_MAXCOUNT)
         hipLaunchKernelGGL(thr_query_max_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
     else hipLaunchKernelGGL(thr_query_sym_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);

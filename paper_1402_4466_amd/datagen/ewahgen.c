@@ -248,3 +248,30 @@ void ewahgen_uniform(uint64_t key, int count, double* out) {
     rng_t r; r.key = key; r.ctr = 0;
     for (int i = 0; i < count; ++i) out[i] = rng_unit(&r);
 }
+
+/*
+ * Bitmaps of a bitmap index from row lists: bitmap i holds the rows
+ * rows[row_off[i] .. row_off[i+1]) (strictly increasing, each < n_bits) and is
+ * written canonically into out + out_off[i], at most out_off[i+1] - out_off[i]
+ * words.  n_out[i] gets its word count, or (uint64_t)-1 if that room was too
+ * small (2 * rows + 2 words, or ceil(n_bits/64) + 1, always suffice).
+ */
+void ewahgen_rows_batch(int count, const uint64_t* row_off, const uint32_t* rows, uint64_t n_bits,
+                        const uint64_t* out_off, uint64_t* out, uint64_t* n_out) {
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int i = 0; i < count; ++i) {
+        writer_t w; memset(&w, 0, sizeof w);
+        w.out = out + out_off[i]; w.cap = out_off[i + 1] - out_off[i]; w.mk = -1;
+        sink_t s; s.w = &w; s.n_bits = n_bits; s.U = (n_bits + 63) >> 6; s.cur_idx = 0; s.cur = 0;
+        uint64_t j = row_off[i], e = row_off[i + 1];
+        int bad = 0;
+        while (j < e) {                     /* consecutive rows become one run */
+            uint64_t a = rows[j], b = a + 1;
+            if (a >= n_bits || (j > row_off[i] && a <= rows[j - 1])) { bad = 1; break; }
+            ++j;
+            while (j < e && rows[j] == b && b < n_bits) { ++b; ++j; }
+            s_set_run(&s, a, b);
+        }
+        n_out[i] = bad ? (uint64_t)(-1) : (n_bits ? s_finish(&s) : w_finish(&w));
+    }
+}

@@ -71,6 +71,7 @@ _symmetric = _sig("ewah_symmetric", _i32, [ctypes.POINTER(_vp), _u32, _vp, _u32,
 _opt_threshold = _sig("ewah_opt_threshold", _i32, [ctypes.POINTER(_vp), _u32, _u64, _vp, _u64, _vp,
                                                    ctypes.POINTER(_u32), _vp])
 _variant_code = _sig("ewah_variant_code", _u32, [_i32, _u32, _u32])
+_variant_code_ex = _sig("ewah_variant_code_ex", _u32, [_i32, _u32, _u32, _i32])
 _default_variant = _sig("ewah_default_variant", _u32, [])
 _batch_plan = _sig("ewah_batch_plan", _i32, [ctypes.POINTER(_vp), _u32, ctypes.POINTER(Query), _u32,
                                              ctypes.POINTER(BatchConfig), ctypes.POINTER(_vp)])
@@ -97,7 +98,7 @@ _mlp_last_error = _sig("ewah_mlp_last_error", ctypes.c_char_p, [])
 EXPORTED = ["ewah_init", "ewah_last_error", "ewah_register", "ewah_register_many", "ewah_release",
             "ewah_get_stats", "ewah_device_words", "ewah_output_bound", "ewah_threshold", "ewah_threshold_v",
             "ewah_symmetric", "ewah_opt_threshold",
-            "ewah_variant_code", "ewah_default_variant", "ewah_batch_plan", "ewah_batch_run",
+            "ewah_variant_code", "ewah_variant_code_ex", "ewah_default_variant", "ewah_batch_plan", "ewah_batch_run",
             "ewah_batch_set_variants", "ewah_batch_set_grid", "ewah_batch_free", "ewah_device_errors",
             "ewah_num_cus", "ewah_query_features", "ewah_batch_features", "ewah_batch_select",
             "ewah_batch_get_variants", "ewah_mlp_create", "ewah_mlp_free", "ewah_mlp_num_params",
@@ -137,7 +138,9 @@ def output_bound(n_bits: int, sum_input_words: int) -> int:
     return int(_output_bound(n_bits, sum_input_words))
 
 
-def variant_code(dense: bool, walk: int, litwalk: int) -> int:
+def variant_code(dense: bool, walk: int, litwalk: int, looped: bool = False) -> int:
+    if looped:
+        return int(_variant_code_ex(1 if dense else 0, walk, litwalk, 1))
     return int(_variant_code(1 if dense else 0, walk, litwalk))
 
 
@@ -251,6 +254,7 @@ class Batch:
         _check(_batch_plan(pool_arr, len(pool), qs, nq, ctypes.byref(cfg), ctypes.byref(h)), "batch_plan")
         self._h = h
         self.nq = nq
+        self.grid = grid          # 0: the library default (as many workgroups as are resident at once)
 
     def run(self, stream=None):
         _check(_batch_run(self._h, _stream_ptr(stream)), "batch_run")
@@ -262,6 +266,7 @@ class Batch:
 
     def set_grid(self, grid: int):
         _check(_batch_set_grid(self._h, grid), "batch_set_grid")
+        self.grid = grid
 
     def features(self, feat_ptr: int, stream=None):
         _check(_batch_features(self._h, feat_ptr, _stream_ptr(stream)), "batch_features")

@@ -2,8 +2,8 @@
 
 Every variant ("arm") computes the same canonical result; they differ in how
 the tile routine spends its work (dense carry-save rows or sparse ripple adds
-for whole-tile dirty runs; how long a segment may be before it is split across
-a wavefront).  Three selectors share one interface:
+for whole-tile dirty runs; a binary or a unary per-row counter; how long a
+segment may be before it is split across a wavefront).  Three selectors share one interface:
 
   MLPSelector   learned cost model: features computed on the device from the
                 registration catalog, FP32 MLP (HIP kernels) predicting the
@@ -31,20 +31,28 @@ DEFAULT_MODEL = os.path.join(HERE, "selector_model.json")
 
 N_FEATURES = 16
 
-# Arms: (name, dense, walk, litwalk).  All compute identical outputs.
+# Arms: (name, dense, walk, litwalk, looped).  All compute identical outputs.
+#   sparse_*  bit-sliced binary counter, every dirty word added by ripple carry
+#             (the accumulator of BSTM, Section 5.3.1);
+#   hybrid_*  the same, with inputs whose dirty run covers a whole tile summed by
+#             a carry-save-adder tree (a sideways-sum circuit);
+#   looped_*  unary saturating counter with levels 1..T (the Looped recurrence,
+#             Section 6.2); taken when T <= bit length of N, else as sparse_*.
 ARMS = [
-    ("hybrid_w8", True, 8, 8),
-    ("sparse_w8", False, 8, 8),
-    ("hybrid_coop", True, 0, 0),
-    ("sparse_walk64", False, 64, 64),
-    ("hybrid_walk32", True, 32, 64),
-    ("hybrid_walk128", True, 128, 255),
+    ("hybrid_w8", True, 8, 8, False),
+    ("sparse_w8", False, 8, 8, False),
+    ("hybrid_coop", True, 0, 0, False),
+    ("sparse_walk64", False, 64, 64, False),
+    ("hybrid_walk32", True, 32, 64, False),
+    ("hybrid_walk128", True, 128, 255, False),
+    ("looped_w8", False, 8, 8, True),
+    ("looped_coop", False, 0, 0, True),
 ]
 
 
 def arm_codes():
     from . import ewahthr as E
-    return [E.variant_code(d, w, l) for (_, d, w, l) in ARMS]
+    return [E.variant_code(d, w, l, looped=lp) for (_, d, w, l, lp) in ARMS]
 
 
 def features_host(queries, stats, n_bits: int) -> np.ndarray:

@@ -76,6 +76,8 @@ def test_variant_codes(E):
     c = E.variant_code(False, 64, 200)
     assert c & 1 == 0 and (c >> 8) & 0xFF == 64 and (c >> 16) & 0xFF == 200
     assert E.variant_code(True, 0, 0) & 1 == 1
+    lp = E.variant_code(False, 8, 8, looped=True)
+    assert lp == E.variant_code(False, 8, 8) | (1 << 24) and not E.variant_code(False, 8, 8) & (1 << 24)
     from paper_1402_4466_amd import selector as S
     codes = S.arm_codes()
     assert len(set(codes)) == len(codes) == len(S.ARMS)

@@ -52,11 +52,12 @@ def _plain_all_T(G, w, variants):
 
 def test_config2_full(G):
     E = G.lib()
-    _plain_all_T(G, D.config2(), [0, E.variant_code(False, 0, 0)])
+    _plain_all_T(G, D.config2(), [0, E.variant_code(False, 0, 0), E.variant_code(False, 8, 8, looped=True)])
 
 
 def test_config3_full(G):
-    _plain_all_T(G, D.config3(), [0])
+    E = G.lib()
+    _plain_all_T(G, D.config3(), [0, E.variant_code(False, 8, 8, looped=True)])
 
 
 def test_batched_full_size_sampled(G):

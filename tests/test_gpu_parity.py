@@ -46,7 +46,10 @@ def _variants(E):
             E.variant_code(False, 255, 255),  # everything walked by single lanes
             E.variant_code(True, 0, 0),       # dense CSA + cooperative
             E.variant_code(True, 4, 16),
-            E.variant_code(True, 32, 64)]
+            E.variant_code(True, 32, 64),
+            E.variant_code(False, 0, 0, looped=True),     # unary counter (T <= bit length of N), cooperative
+            E.variant_code(False, 255, 255, looped=True),  # unary counter, walked by single lanes
+            E.variant_code(True, 8, 8, looped=True)]       # dense flag ignored by the unary counter
 
 
 def _check(G, streams, n_bits, Ts, variants=(0,), label=""):
@@ -206,7 +209,8 @@ def test_batched_matches_plain_and_oracle(G):
     for q in qs:
         o, n, c = G.alloc_out(n_bits, int(sum(len(pool[i]) for i in q.idx)))
         outs.append(o); ns.append(n); caps.append(c)
-    variants = [_variants(E)[i % 6] for i in range(len(qs))]
+    vs = _variants(E)
+    variants = [vs[i % len(vs)] for i in range(len(qs))]
     batch = E.Batch(bms, [(q.idx, q.T) for q in qs], [o.data_ptr() for o in outs], caps,
                     [n.data_ptr() for n in ns], variants=variants, use_graph=True)
     wants = [O.threshold([pool[i] for i in q.idx], n_bits, q.T, want_hist=False)[0] for q in qs]
