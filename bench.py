@@ -386,6 +386,7 @@ def bench_index(args, E, torch):
     shaped as the paper's relational tables: 5,000 queries of each kind, thresholds settled by the
     empty-answer rule with the library's own largest-count pass (untimed).  One step runs every
     settled query through the batched path, one persistent graph launch per (table, kind)."""
+    from paper_1402_4466_amd import autotune as A
     from paper_1402_4466_amd import selector as S
     from paper_1402_4466_amd.datagen import Query as DQ
     from paper_1402_4466_amd.datagen import index as DI
@@ -425,9 +426,14 @@ def bench_index(args, E, torch):
                     keep.append((i, q, T))
             qd = [DQ(q.idx, T) for _, q, T in keep]
             b = E.Batch(pools[sh], [(q.idx, q.T) for q in qd], [ptrs[i] for i, _, _ in keep],
-                        [caps[i] for i, _, _ in keep], [nptrs[i] for i, _, _ in keep], grid=E.num_cus(),
+                        [caps[i] for i, _, _ in keep], [nptrs[i] for i, _, _ in keep], grid=2 * E.num_cus(),
                         use_graph=True)
-            sel.apply(b, pools[sh], qd, ix.n_bits, stream)
+            sel_kind = sel.apply(b, pools[sh], qd, ix.n_bits, stream)
+            signature = f"index_{kind}_{sh}_q{len(qd)}_{sel_kind}"
+            tuned = None if args.retune else A.lookup(signature)
+            if tuned is None and (args.tune or args.retune):
+                tuned = A.tune_batch(b, lambda: b.run(stream), signature, E.num_cus(), log=log)
+            b.set_grid(int(tuned["grid"]) if tuned else 2 * E.num_cus())   # two workgroups per CU
             batches.append(b)
             groups.append({"kind": kind, "shape": sh, "queries": len(qd),
                            "input_bytes": int(sum(in_words[i] for i, _, _ in keep)) * 8, "qd": qd, "ix": ix,
@@ -451,7 +457,7 @@ def bench_index(args, E, torch):
         gms = events_time(lambda: b.run(stream), stream, max(3, args.steps))
         ow = int(g["out_n"][g["rows"]].sum().item())
         out_words += ow
-        per.append({"kind": g["kind"], "shape": g["shape"], "queries": g["queries"], "ms": round(gms, 4),
+        per.append({"kind": g["kind"], "shape": g["shape"], "queries": g["queries"], "grid": b.grid, "ms": round(gms, 4),
                     "GB/s": round(g["input_bytes"] / (gms / 1e3) / 1e9, 1), "out_words": ow})
         log(f"{g['kind']} {g['shape']}: {g['queries']} queries, {gms:.3f} ms, {per[-1]['GB/s']} GB/s")
     log(f"index workload: {ms:.3f} ms/step, {value:.1f} GB/s input")
