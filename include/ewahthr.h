@@ -146,14 +146,26 @@ ewah_status ewah_symmetric(const ewah_bitmap* const* in, uint32_t n, const uint8
  * largest T with a non-empty result, which is the largest row count, as
  * ScanCount finds it from its counters, Section 5.1) and returns that result.
  * *T_out (host memory) receives T; output buffers, bound and errors as for
- * ewah_threshold.  1 <= K <= n_bits, else EINVAL.  One pass over the inputs
- * finds the largest count (tiles that cannot exceed the largest count seen so
- * far are skipped); K > 1 adds a binary search over T with one counting pass
- * per step.  The call is synchronous: it returns once T is known and the
- * result has been enqueued on hip_stream.
+ * ewah_threshold.  1 <= K <= n_bits, else EINVAL.  K = 1: one pass over the
+ * inputs finds the largest count (tiles that cannot exceed the largest count
+ * seen so far are skipped); K > 1: one pass builds the count histogram
+ * (ewah_count_histogram) and T is the largest count whose suffix sum reaches
+ * K.  The call is synchronous: it returns once T is known and the result has
+ * been enqueued on hip_stream.
  */
 ewah_status ewah_opt_threshold(const ewah_bitmap* const* in, uint32_t n, uint64_t K, uint64_t* out_words_dev,
                                uint64_t out_cap, uint64_t* out_n_words_dev, uint32_t* T_out, void* hip_stream);
+
+/*
+ * Count histogram (the counters of ScanCount, Section 5.1, summarised):
+ * hist[c] = number of rows set in exactly c of the n inputs, c = 0..n.  hist
+ * is host memory of n + 1 entries, owned by the caller.  Every opt-threshold
+ * (Section 3.3) follows from it: the T-of-N result has sum over c >= T of
+ * hist[c] rows.  Inputs as for ewah_threshold (1 <= n <= 4095, one n_bits);
+ * no output bitmap is written.  Synchronous on hip_stream.  EINVAL for a null
+ * or empty input list or a null hist.
+ */
+ewah_status ewah_count_histogram(const ewah_bitmap* const* in, uint32_t n, uint64_t* hist, void* hip_stream);
 
 /* As ewah_threshold with an explicit kernel variant (ewah_variant_code); the result is identical. */
 ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,

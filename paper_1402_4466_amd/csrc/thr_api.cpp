@@ -57,8 +57,8 @@ struct Ctx {                       // per-stream query state
     uint32_t* d_ticket = nullptr;  // tile order of the single-query kernel
     uint32_t epoch = 0;
     hipEvent_t ev = nullptr;       // staging buffer free once this completes
-    unsigned long long* d_acc = nullptr;   // opt-threshold: largest count / output row count
-    unsigned long long* h_acc = nullptr;   // pinned copy
+    unsigned long long* d_acc = nullptr;   // opt-threshold: largest count / output row count / histogram
+    unsigned long long* h_acc = nullptr;   // pinned copy (MAXN + 1 values)
 };
 
 struct Lib {
@@ -447,7 +447,9 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
                       void* hip_stream) {
     ewah_status st = ensure_ready();
     if (st) return st;
-    if ((n && !in) || !out_n_words_dev) return fail(EWAH_EINVAL, "null argument");
+    // the largest-count and histogram passes write no output
+    const bool writes = !pred || (pred->kind != PRED_MAXCOUNT && pred->kind != PRED_HIST);
+    if ((n && !in) || (writes && !out_n_words_dev)) return fail(EWAH_EINVAL, "null argument");
     if (n > MAXN) return fail(EWAH_EINVAL, "at most " + std::to_string(MAXN) + " inputs per query");
     if (n == 0) return fail(EWAH_EINVAL, "n = 0: the number of rows is undefined without an input");
     uint64_t n_bits = 0, sum_words = 0;
@@ -457,14 +459,14 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
         else if (in[i]->stats.n_bits != n_bits) return fail(EWAH_EINVAL, "inputs have different n_bits");
         sum_words += in[i]->stats.n_words;
     }
-    const uint64_t bound = ewah_output_bound(n_bits, sum_words);
+    const uint64_t bound = writes ? ewah_output_bound(n_bits, sum_words) : 0;
     if (out_cap < bound)
         return fail(EWAH_ENOSPC, "out_cap " + std::to_string(out_cap) + " < bound " + std::to_string(bound));
     if (bound && !out_words_dev) return fail(EWAH_EINVAL, "null output");
     hipStream_t s = (hipStream_t)hip_stream;
     const uint32_t U = (uint32_t)((n_bits + 63) / 64);
     if (U == 0) {
-        HIPCHK(launch_zero_len(out_n_words_dev, s));
+        if (writes) HIPCHK(launch_zero_len(out_n_words_dev, s));
         return EWAH_OK;
     }
     const uint32_t tiles = (U + TW - 1) / TW;
@@ -504,23 +506,42 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
 }
 
 // Runs one query whose predicate record accumulates into the stream's accumulator
-// and returns the accumulated value (synchronous).
+// (n_values words, cleared first) and returns the accumulated values (synchronous).
 ewah_status run_accumulate(const ewah_bitmap* const* in, uint32_t n, PredDev& pd, uint64_t* out_words_dev,
-                           uint64_t out_cap, uint64_t* out_n_words_dev, hipStream_t s, uint64_t& value) {
+                           uint64_t out_cap, uint64_t* out_n_words_dev, hipStream_t s, uint64_t* values,
+                           uint32_t n_values = 1) {
     Ctx* c = nullptr;
     ewah_status st = get_ctx(s, &c);
     if (st) return st;
+    if (n_values == 0 || n_values > MAXN + 1) return fail(EWAH_EINVAL, "accumulator size");
     if (!c->d_acc) {
-        HIPCHK(hipMalloc(&c->d_acc, 16));
-        HIPCHK(hipHostMalloc(&c->h_acc, 16, hipHostMallocDefault));
+        HIPCHK(hipMalloc(&c->d_acc, (MAXN + 1) * 8));
+        HIPCHK(hipHostMalloc(&c->h_acc, (MAXN + 1) * 8, hipHostMallocDefault));
     }
-    HIPCHK(hipMemsetAsync(c->d_acc, 0, 8, s));
+    HIPCHK(hipMemsetAsync(c->d_acc, 0, (size_t)n_values * 8, s));
     pd.acc = c->d_acc;
     st = run_plain(in, n, pd.tz, &pd, out_words_dev, out_cap, out_n_words_dev, 0, s);
     if (st) return st;
-    HIPCHK(hipMemcpyAsync(c->h_acc, c->d_acc, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c->h_acc, c->d_acc, (size_t)n_values * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    value = *c->h_acc;
+    std::memcpy(values, c->h_acc, (size_t)n_values * 8);
+    return EWAH_OK;
+}
+
+// Count histogram: hist[c] = rows with exactly c of the n inputs set, c = 0..n (synchronous).
+ewah_status count_histogram(const ewah_bitmap* const* in, uint32_t n, uint64_t* hist, hipStream_t s) {
+    if (!hist) return fail(EWAH_EINVAL, "null histogram");
+    if (n == 0 || !in) return fail(EWAH_EINVAL, "n = 0: the number of rows is undefined without an input");
+    if (n > MAXN) return fail(EWAH_EINVAL, "at most " + std::to_string(MAXN) + " inputs per query");
+    if (!in[0]) return fail(EWAH_EINVAL, "null bitmap at index 0");
+    PredDev pd{};
+    pd.kind = PRED_HIST;
+    pd.tz = 1;
+    ewah_status st = run_accumulate(in, n, pd, nullptr, 0, nullptr, s, hist, n + 1);
+    if (st) return st;
+    uint64_t set = 0;
+    for (uint32_t c = 1; c <= n; ++c) set += hist[c];
+    hist[0] = in[0]->stats.n_bits - set;
     return EWAH_OK;
 }
 
@@ -582,31 +603,39 @@ ewah_status ewah_opt_threshold(const ewah_bitmap* const* in, uint32_t n, uint64_
     if (n && in && in[0] && (K == 0 || K > in[0]->stats.n_bits))
         return fail(EWAH_EINVAL, "K must be in [1, n_bits]");
     hipStream_t s = (hipStream_t)hip_stream;
-    // the largest row count M (one pass, branch and bound over the tiles)
-    PredDev pd{};
-    pd.kind = PRED_MAXCOUNT;
-    pd.tz = 1;
-    uint64_t M = 0;
-    ewah_status st = run_accumulate(in, n, pd, out_words_dev, out_cap, out_n_words_dev, s, M);
-    if (st) return st;
-    uint32_t best = (uint32_t)M;   // K = 1: the rows of count M exist (T = 0 if no row is set)
-    if (K > 1 && M > 0) {
-        // largest T in [0, M] whose result has at least K rows; T = 0 gives all n_bits >= K rows
-        uint32_t lo = 0, hi = (uint32_t)M;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) / 2;
-            PredDev tp{};
-            tp.kind = PRED_THRESHOLD;
-            tp.tz = mid;
-            uint64_t rows = 0;
-            st = run_accumulate(in, n, tp, out_words_dev, out_cap, out_n_words_dev, s, rows);
-            if (st) return st;
-            if (rows >= K) lo = mid; else hi = mid - 1;
+    ewah_status st;
+    uint32_t best = 0;
+    if (K == 1) {
+        // the largest row count M (one pass, branch and bound over the tiles): the rows of
+        // count M exist (T = 0 if no row is set)
+        PredDev pd{};
+        pd.kind = PRED_MAXCOUNT;
+        pd.tz = 1;
+        uint64_t M = 0;
+        st = run_accumulate(in, n, pd, out_words_dev, out_cap, out_n_words_dev, s, &M);
+        if (st) return st;
+        best = (uint32_t)M;
+    } else {
+        // the count histogram (one pass): the largest T whose suffix sum reaches K; T = 0
+        // gives all n_bits >= K rows
+        if (n > MAXN) return fail(EWAH_EINVAL, "at most " + std::to_string(MAXN) + " inputs per query");
+        std::vector<uint64_t> hist((size_t)n + 1);
+        st = count_histogram(in, n, hist.data(), s);
+        if (st) return st;
+        uint64_t above = 0;
+        for (uint32_t T = n; T >= 1; --T) {
+            above += hist[T];
+            if (above >= K) { best = T; break; }
         }
-        best = lo;
     }
     *T_out = best;
     return run_plain(in, n, best, nullptr, out_words_dev, out_cap, out_n_words_dev, 0, hip_stream);
+}
+
+ewah_status ewah_count_histogram(const ewah_bitmap* const* in, uint32_t n, uint64_t* hist, void* hip_stream) {
+    ewah_status st = ensure_ready();
+    if (st) return st;
+    return count_histogram(in, n, hist, (hipStream_t)hip_stream);
 }
 
 ewah_status ewah_symmetric(const ewah_bitmap* const* in, uint32_t n, const uint8_t* f, uint32_t f_len,

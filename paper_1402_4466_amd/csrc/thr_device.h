@@ -116,6 +116,7 @@ enum : uint32_t {
     PRED_ODD = 2,         // count odd (XOR of the inputs)
     PRED_EVEN = 3,        // count even
     PRED_MAXCOUNT = 4,    // no output: the largest row count goes to *acc (atomic maximum)
+    PRED_HIST = 5,        // no output: acc[c] += rows of count c, for c = 1..N (count histogram)
 };
 constexpr int MAX_IV = 8;
 

@@ -529,7 +529,9 @@ static_assert(PCAP_FINE / 4 < 256u && PCAP_COARSE / 16 < 256u, "byte counters");
 // STAGED: the tile writes its words to the staging area and publishes its
 // aggregate (a placement pass finishes the output); otherwise it finds the prefix
 // over earlier tiles by look-back and writes its words in place.
-template <bool STAGED, bool GENERAL = false, bool MAXC = false, bool LOOPED = false>
+static_assert((MAXN + 1u) * 4u <= (uint32_t)WCAP * 16u, "count histogram must fit in the window list");
+
+template <bool STAGED, bool GENERAL = false, bool MAXC = false, bool LOOPED = false, bool HIST = false>
 __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ table, uint32_t t,
                              uint32_t epoch, unsigned char* smem, uint32_t* err, uint32_t dbg_slot) {
     (void)dbg_slot;   // timestamp slot of debug builds
@@ -571,7 +573,8 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     // largest count: the running maximum over the tiles done so far bounds what is
     // worth counting (branch and bound); no tile is trivial
     uint32_t Rmax = 0;
-    if constexpr (MAXC) {
+    if constexpr (HIST) trivial = false;
+    if constexpr (MAXC && !HIST) {
         trivial = false;
         Rmax = (uint32_t)__builtin_amdgcn_readfirstlane(
             (int)(uint32_t)__hip_atomic_load(q.pd->acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -641,7 +644,22 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         Tz = (uint32_t)__builtin_amdgcn_readfirstlane((int)q.pd->tz);
         v0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)q.pd->v0);
     }
-    if constexpr (MAXC) {
+    if constexpr (HIST) {
+        // counts of zero are not tallied; a tile whose inputs that can hold a one are all
+        // full one-fills has every row at that count
+        const uint32_t lo = misc[M_ONEFULL], hi = misc[M_NONZERO];
+        if (hi == 0) return;
+        if (lo >= hi) {
+            if (tid == 0) {
+                const bool last = tS + nPos == U;
+                const uint64_t rows = 64ull * nPos - ((last && q.tail_bits) ? 64ull - q.tail_bits : 0ull);
+                atomicAdd(q.pd->acc + hi, (unsigned long long)rows);
+            }
+            return;
+        }
+        mode = 0u;
+        Tz = 1u;   // groups no input touches hold counts of zero
+    } else if constexpr (MAXC) {
         // every count of the tile is at most the number of inputs that can hold a one
         // there; if those are all full one-fills, every count equals it
         const uint32_t lo = misc[M_ONEFULL], hi = misc[M_NONZERO];
@@ -878,7 +896,41 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     uint32_t k1tot;
     int32_t dv = tid < TW ? diff[tid] : 0;
     uint32_t k1 = block_excl_scan((uint32_t)dv, misc + M_TMP, k1tot) + (uint32_t)dv;
-    if constexpr (MAXC) {
+    if constexpr (HIST) {
+        // count histogram of the tile in LDS (the window list is free now), then added
+        // into acc[1..N]: the count of a row is its planes value plus the one-fills at
+        // its word; rows of count zero are skipped
+        uint32_t* hl = (uint32_t*)win;
+        for (uint32_t i = (uint32_t)tid; i <= N; i += BLOCK) hl[i] = 0u;
+        __syncthreads();
+        if ((uint32_t)tid < nPos) {
+            const uint64_t cand = (tS + (uint32_t)tid == U - 1u && q.tail_bits) ? ((1ull << q.tail_bits) - 1ull) : ~0ull;
+            uint64_t R[MAXP];
+            uint64_t any = 0;
+#pragma unroll
+            for (int p = 0; p < MAXP; ++p) {
+                R[p] = p < P ? planes[p * TW + tid] : 0ull;
+                any |= R[p];
+            }
+            any &= cand;
+            if (k1) {
+                const uint32_t c0 = (uint32_t)__popcll(cand & ~any);
+                if (c0) atomicAdd(&hl[k1], c0);
+            }
+            while (any) {
+                const int r = __builtin_ctzll(any);
+                any &= any - 1ull;
+                uint32_t c = 0;
+#pragma unroll
+                for (int p = 0; p < MAXP; ++p) c |= (uint32_t)((R[p] >> r) & 1ull) << p;
+                atomicAdd(&hl[c + k1], 1u);
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = 1u + (uint32_t)tid; i <= N; i += BLOCK)
+            if (hl[i]) atomicAdd(q.pd->acc + i, (unsigned long long)hl[i]);
+        return;
+    } else if constexpr (MAXC) {
         // largest planes value over the word's valid rows (bit-sliced maximum: keep the
         // rows holding the highest plane bit seen so far), plus the position's one-fills
         if ((uint32_t)tid < nPos) {
@@ -1271,6 +1323,20 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_sym_kernel(QueryDev q, con
     process_tile<false, true>(q, table, s_t, epoch, smem, err, s_t);
 }
 
+// Count histogram of a query (q.pd->kind = PRED_HIST): no output is written.
+__global__ __launch_bounds__(BLOCK, 4) void thr_query_hist_kernel(QueryDev q, const BitmapDev* __restrict__ table,
+                                                               uint32_t* ticket, uint32_t epoch, uint32_t* err) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_t;
+    if (threadIdx.x == 0) {
+        uint32_t t = atomicAdd(ticket, 1u);
+        if (t == q.tiles - 1) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_t = t;
+    }
+    __syncthreads();
+    process_tile<false, false, true, false, true>(q, table, s_t, epoch, smem, err, s_t);
+}
+
 // Largest row count of a query (q.pd->kind = PRED_MAXCOUNT): no output is written.
 __global__ __launch_bounds__(BLOCK, 4) void thr_query_max_kernel(QueryDev q, const BitmapDev* __restrict__ table,
                                                           uint32_t* ticket, uint32_t epoch, uint32_t* err) {
@@ -1377,6 +1443,8 @@ hipError_t set_smem_limits(size_t max_bytes) {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void*)thr_query_looped_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)thr_query_hist_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)thr_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
 }
 
@@ -1392,6 +1460,8 @@ hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* tic
     if (!q.pd && use_looped(q.variant, q.N, q.T))
         hipLaunchKernelGGL(thr_query_looped_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
     else if (!q.pd) hipLaunchKernelGGL(thr_query_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
+    else if (pred_kind == PRED_HIST)
+        hipLaunchKernelGGL(thr_query_hist_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
     else if (pred_kind == PRED_MAXCOUNT)
         hipLaunchKernelGGL(thr_query_max_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
     else hipLaunchKernelGGL(thr_query_sym_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);

@@ -68,6 +68,7 @@ _device_words = _sig("ewah_device_words", _vp, [_vp])
 _output_bound = _sig("ewah_output_bound", _u64, [_u64, _u64])
 _threshold_v = _sig("ewah_threshold_v", _i32, [ctypes.POINTER(_vp), _u32, _u32, _vp, _u64, _vp, _u32, _vp])
 _symmetric = _sig("ewah_symmetric", _i32, [ctypes.POINTER(_vp), _u32, _vp, _u32, _vp, _u64, _vp, _vp])
+_count_histogram = _sig("ewah_count_histogram", _i32, [ctypes.POINTER(_vp), _u32, _vp, _vp])
 _opt_threshold = _sig("ewah_opt_threshold", _i32, [ctypes.POINTER(_vp), _u32, _u64, _vp, _u64, _vp,
                                                    ctypes.POINTER(_u32), _vp])
 _variant_code = _sig("ewah_variant_code", _u32, [_i32, _u32, _u32])
@@ -97,7 +98,7 @@ _mlp_last_error = _sig("ewah_mlp_last_error", ctypes.c_char_p, [])
 
 EXPORTED = ["ewah_init", "ewah_last_error", "ewah_register", "ewah_register_many", "ewah_release",
             "ewah_get_stats", "ewah_device_words", "ewah_output_bound", "ewah_threshold", "ewah_threshold_v",
-            "ewah_symmetric", "ewah_opt_threshold",
+            "ewah_symmetric", "ewah_opt_threshold", "ewah_count_histogram",
             "ewah_variant_code", "ewah_variant_code_ex", "ewah_default_variant", "ewah_batch_plan", "ewah_batch_run",
             "ewah_batch_set_variants", "ewah_batch_set_grid", "ewah_batch_free", "ewah_device_errors",
             "ewah_num_cus", "ewah_query_features", "ewah_batch_features", "ewah_batch_select",
@@ -229,6 +230,15 @@ def opt_threshold(bitmaps, K: int, out_words_ptr: int, out_cap: int, out_n_ptr: 
     _check(_opt_threshold(arr, n, K, out_words_ptr, out_cap, out_n_ptr, ctypes.byref(t), _stream_ptr(stream)),
            "opt_threshold")
     return int(t.value)
+
+
+def count_histogram(bitmaps, stream=None) -> np.ndarray:
+    """hist[c] = rows set in exactly c of the inputs, c = 0..len(bitmaps) (the call waits)."""
+    n = len(bitmaps)
+    arr = (_vp * max(n, 1))(*[b.handle for b in bitmaps])
+    hist = np.zeros(n + 1, dtype=np.uint64)
+    _check(_count_histogram(arr, n, hist.ctypes.data, _stream_ptr(stream)), "count_histogram")
+    return hist
 
 
 class Batch:

@@ -1,9 +1,10 @@
 """Opt-threshold on the GPU path (needs an MI355X): the largest T whose result has
 at least K rows (Section 3.3), and that result, against the oracle.
 
-Covers several tiles with a ragged tail, word and 4-word bounds (N up to 300),
+Covers several tiles with a ragged tail, word and 4-word bounds (N up to 1000),
 K from 1 to n_bits, all-zero inputs (T = 0: every row), a single row, the
-full-size config-2 inputs, and the argument checks.
+full-size config-2 inputs, and the argument checks.  The count histogram that
+K > 1 reads (ewah_count_histogram) is compared with the oracle's directly.
 """
 import os
 import re
@@ -94,6 +95,53 @@ def test_config2_full(G):
             T, got = _gpu_opt(G, bms, K)
             print(f"config 2 K={K}: T={T} ({len(got)} words)", flush=True)
             assert T == want_T and np.array_equal(got, want), K
+    finally:
+        for b in bms:
+            b.release()
+    assert E.device_errors() == 0
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_count_histogram_against_oracle(G, case):
+    """ewah_count_histogram against the oracle's ScanCount histogram: word (N <= 256) and
+    4-word (N > 256) bounds, tiles settled as uniform, one-fills, a ragged tail, one row."""
+    E = G.lib()
+    n = [1, 7, 64, 300, 1000, 40][case]
+    n_bits = [1, 3 * TW_ROWS + 77, 2 * TW_ROWS, TW_ROWS + 5, 3000, 5 * TW_ROWS + 1][case]
+    if case == 5:   # long one-fills and zero-fills: tiles where every count is equal
+        streams = D.bitmaps(D.MARKOV, float(TW_ROWS), float(TW_ROWS), n_bits, [D.key(950, k) for k in range(n)])
+    elif case % 2:
+        streams = D.bitmaps(D.MARKOV, 100.0, np.full(n, 1500.0), n_bits, [D.key(940 + case, k) for k in range(n)])
+    else:
+        rng = np.random.default_rng(930 + case)
+        streams = D.bitmaps(D.IID, rng.uniform(0.001, 0.5, n), 0.0, n_bits, [D.key(940 + case, k) for k in range(n)])
+    bms = G.register(streams, n_bits)
+    try:
+        _, want = O.threshold(streams, n_bits, n + 1)
+        got = E.count_histogram(bms)
+        assert np.array_equal(got, want), (n, n_bits)
+        # repeated inputs count once per occurrence
+        twice = bms + bms[: max(1, n // 3)]
+        _, want2 = O.threshold(streams + streams[: max(1, n // 3)], n_bits, len(twice) + 1)
+        assert np.array_equal(E.count_histogram(twice), want2), (n, n_bits, "repeats")
+    finally:
+        for b in bms:
+            b.release()
+    assert E.device_errors() == 0
+
+
+def test_count_histogram_full_config2_and_errors(G):
+    E = G.lib()
+    w = D.config2()
+    bms = G.register(w.streams, w.n_bits)
+    try:
+        _, want = O.threshold(w.streams, w.n_bits, len(w.streams) + 1)
+        got = E.count_histogram(bms)
+        print(f"config 2 histogram: rows of count >= 1: {int(got[1:].sum())}", flush=True)
+        assert np.array_equal(got, want)
+        with pytest.raises(E.EwahError) as e:
+            E.count_histogram([])
+        assert e.value.code == E.EINVAL
     finally:
         for b in bms:
             b.release()

@@ -4,6 +4,7 @@
   holds at least K rows;
 * K = 1: the result is exactly the set of rows whose count equals the largest
   count (the ScanCount reading of Section 5.1);
+* the count histogram against row membership counted in decoded row sets;
 * at larger sizes, the defining property |result(T)| >= K > |result(T + 1)|, with
   row counts taken as popcounts of decoded threshold results.
 """
@@ -63,3 +64,19 @@ def test_defining_property():
             if T < n:
                 nxt, _ = O.threshold(streams, n_bits, T + 1, want_hist=False)
                 assert _popcount(nxt, n_bits) < K, (n, K)
+
+
+def test_count_histogram_brute_force():
+    """The oracle's count histogram (hist[c] = rows set in exactly c inputs) against
+    counting row membership in decoded row sets, including non-canonical streams."""
+    rng = np.random.default_rng(23)
+    for case in range(20):
+        n = int(rng.integers(1, 7))
+        n_bits = int(rng.integers(1, 400))
+        dens = rng.uniform(0.02, 0.8, n)
+        streams = D.bitmaps(D.IID, dens, 0.0, n_bits, [D.key(7100 + case, k) for k in range(n)],
+                            noncanon=bool(case % 2))
+        sets = [_rows(s, n_bits) for s in streams]
+        counts = [sum(1 for s in sets if row in s) for row in range(n_bits)]
+        _, hist = O.threshold(streams, n_bits, n + 1)
+        assert [int(h) for h in hist] == [counts.count(c) for c in range(n + 1)], case
