@@ -10,7 +10,8 @@
   the oracle; every other output is checked for properties that hold at any
   size: it decodes to exactly U words, it is canonical (re-encoding it gives it
   back), and its length respects the output bound;
-* degenerate shapes and the input-count limit.
+* degenerate shapes and the input-count limit (N = 4095: threshold, the unary counter at its
+  12 levels, the 4,096-bin count histogram, opt-threshold and a symmetric function).
 """
 import sys
 
@@ -139,9 +140,25 @@ def test_input_count_limit(G):
             want, _ = O.threshold(streams, n_bits, T, want_hist=False)
             got = G.gpu_threshold(bms, T)
             assert np.array_equal(got, want), T
+        # the unary counter at its largest level count (T = bit length of N = 12)
+        want, hist = O.threshold(streams, n_bits, 12)
+        assert np.array_equal(G.gpu_threshold(bms, 12, variant=E.variant_code(False, 8, 8, looped=True)), want)
+        # count histogram (N + 1 = 4096 bins, the LDS bin capacity), opt-threshold, a symmetric function
+        assert np.array_equal(E.count_histogram(bms), hist)
+        out, out_n, cap = G.alloc_out(n_bits, sum(len(s) for s in streams))
+        for K in (1, 50):
+            want_T, want_words = O.opt_threshold(streams, n_bits, K)
+            assert E.opt_threshold(bms, K, out.data_ptr(), cap, out_n.data_ptr()) == want_T, K
+            assert np.array_equal(G.fetch(out, out_n), want_words), K
+        f = [1 if 2 <= c <= 5 else 0 for c in range(n + 1)]
+        E.symmetric(bms, f, out.data_ptr(), cap, out_n.data_ptr())
+        assert np.array_equal(G.fetch(out, out_n), O.symmetric(streams, n_bits, f))
         out, out_n, cap = G.alloc_out(n_bits, sum(len(s) for s in streams) * 2)
         with pytest.raises(E.EwahError) as e:
             E.threshold(bms + bms[:1], 1, out.data_ptr(), cap, out_n.data_ptr())
+        assert e.value.code == E.EINVAL
+        with pytest.raises(E.EwahError) as e:
+            E.count_histogram(bms + bms[:1])
         assert e.value.code == E.EINVAL
     finally:
         for b in bms:
