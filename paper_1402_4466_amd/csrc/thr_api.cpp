@@ -59,6 +59,14 @@ struct Ctx {                       // per-stream query state
     hipEvent_t ev = nullptr;       // staging buffer free once this completes
     unsigned long long* d_acc = nullptr;   // opt-threshold: largest count / output row count / histogram
     unsigned long long* h_acc = nullptr;   // pinned copy (MAXN + 1 values)
+    // single threshold queries of many tiles run through the persistent batched kernel
+    // (staged tiles, scan, placement) as a batch of one: its own tile states (tagged with
+    // the device epoch at work1[1]), staging area and item-to-query map (all zeros)
+    TileState* d_state1 = nullptr;
+    uint64_t* d_stage1 = nullptr;
+    uint32_t* d_tq1 = nullptr;
+    size_t tiles1_cap = 0;
+    uint32_t* d_work1 = nullptr;
 };
 
 struct Lib {
@@ -274,6 +282,40 @@ ewah_status ctx_reserve(Ctx& c, hipStream_t s, size_t n_ids, size_t tiles) {
     return EWAH_OK;
 }
 
+// Buffers of the one-query batched run for queries of up to `tiles` tiles.
+ewah_status ctx_reserve_batched(Ctx& c, hipStream_t s, size_t tiles) {
+    if (!c.d_work1) {
+        HIPCHK(hipMalloc(&c.d_work1, WORK_WORDS * 4));
+        HIPCHK(hipMemset(c.d_work1, 0, WORK_WORDS * 4));
+    }
+    if (tiles > c.tiles1_cap) {
+        HIPCHK(hipStreamSynchronize(s));   // earlier runs on this stream may still use the old buffers
+        if (c.d_state1) HIPCHK(hipFree(c.d_state1));
+        if (c.d_stage1) HIPCHK(hipFree(c.d_stage1));
+        if (c.d_tq1) HIPCHK(hipFree(c.d_tq1));
+        c.d_state1 = nullptr; c.d_stage1 = nullptr; c.d_tq1 = nullptr; c.tiles1_cap = 0;
+        const size_t cap = std::max<size_t>(tiles, 1024);
+        HIPCHK(hipMalloc(&c.d_state1, cap * sizeof(TileState)));
+        HIPCHK(hipMemset(c.d_state1, 0, cap * sizeof(TileState)));
+        if (hipMalloc(&c.d_stage1, cap * STAGE_WORDS * sizeof(uint64_t)) != hipSuccess)
+            return fail(EWAH_ENOMEM, "staging area of " + std::to_string(cap * STAGE_WORDS * 8) + " bytes");
+        HIPCHK(hipMalloc(&c.d_tq1, cap * 4));
+        HIPCHK(hipMemset(c.d_tq1, 0, cap * 4));
+        c.tiles1_cap = cap;
+    }
+    return EWAH_OK;
+}
+
+// Resident workgroups of the batched kernel at a given LDS size (cached per size).
+uint32_t batch_resident(size_t smem) {
+    static std::map<size_t, uint32_t> cache;
+    auto it = cache.find(smem);
+    if (it != cache.end()) return it->second;
+    const uint32_t r = g.n_cu * (uint32_t)batch_blocks_per_cu(smem);
+    cache[smem] = r;
+    return r;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------- C ABI
@@ -472,27 +514,35 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
     const uint32_t tiles = (U + TW - 1) / TW;
     // staging: the n slots, then (8-byte aligned) the predicate record
     const size_t pred_off = ((size_t)n + 1) & ~(size_t)1;
-    const size_t n_stage = pred ? pred_off + sizeof(PredDev) / 4 : n;
+    size_t n_stage = pred ? pred_off + sizeof(PredDev) / 4 : n;
+    // A threshold query with more tiles than twice the resident workgroups runs as a
+    // batch of one on the persistent kernel: its tiles are taken in turn from per-XCD
+    // ranges and placed by a scan, instead of one workgroup per tile chained by
+    // look-back.  Its query record and item range {0, tiles} are staged after the slots.
+    const size_t smem = tile_smem_bytes(n);
+    const uint32_t resident = batch_resident(smem);
+    const bool batched = !pred && tiles >= 2u * resident;
+    size_t q_off = 0, qt_off = 0;
+    if (batched) {
+        q_off = (n_stage + 1) & ~(size_t)1;          // 8-byte aligned
+        qt_off = q_off + sizeof(QueryDev) / 4;
+        n_stage = qt_off + 2;
+    }
     Ctx* c = nullptr;
     st = get_ctx(s, &c);
     if (st) return st;
     st = ctx_reserve(*c, s, n_stage, tiles);
     if (st) return st;
-    HIPCHK(hipEventSynchronize(c->ev));   // previous upload from the staging buffer is done
-    for (uint32_t i = 0; i < n; ++i) c->h_ids[i] = in[i]->slot;
-    if (pred) std::memcpy(c->h_ids + pred_off, pred, sizeof(PredDev));
-    HIPCHK(hipMemcpyAsync(c->d_ids, c->h_ids, n_stage * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipEventRecord(c->ev, s));
-    if ((++c->epoch & 0xFFFFu) == 0) {   // 16-bit tags wrapped: clear stale states
-        HIPCHK(hipMemsetAsync(c->d_state, 0, c->state_cap * sizeof(TileState), s));
-        c->epoch = 1;
+    if (batched) {
+        st = ctx_reserve_batched(*c, s, tiles);
+        if (st) return st;
     }
     QueryDev q{};
     q.ids = c->d_ids;
     q.out = out_words_dev;
     q.out_n = out_n_words_dev;
-    q.state = c->d_state;
-    q.stage = nullptr;             // the single-query kernel writes its output in place
+    q.state = batched ? c->d_state1 : c->d_state;
+    q.stage = batched ? c->d_stage1 : nullptr;   // the single-query kernel writes its output in place
     q.cap = out_cap;
     q.N = n;
     q.T = pred ? pred->tz : T;
@@ -501,6 +551,26 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
     q.tail_bits = (uint32_t)(n_bits % 64);
     q.variant = variant ? variant : ewah_default_variant();
     q.pd = pred ? (const PredDev*)(c->d_ids + pred_off) : nullptr;
+    HIPCHK(hipEventSynchronize(c->ev));   // previous upload from the staging buffer is done
+    for (uint32_t i = 0; i < n; ++i) c->h_ids[i] = in[i]->slot;
+    if (pred) std::memcpy(c->h_ids + pred_off, pred, sizeof(PredDev));
+    if (batched) {
+        std::memcpy(c->h_ids + q_off, &q, sizeof(QueryDev));
+        c->h_ids[qt_off] = 0u;
+        c->h_ids[qt_off + 1] = tiles;
+    }
+    HIPCHK(hipMemcpyAsync(c->d_ids, c->h_ids, n_stage * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(c->ev, s));
+    if (batched) {
+        HIPCHK(launch_bump(c->d_work1, s));
+        HIPCHK(launch_batch((const QueryDev*)(c->d_ids + q_off), c->d_ids + qt_off, c->d_tq1, 1u, tiles, g.d_table,
+                            c->d_work1, c->d_work1 + 1, g.d_err, resident, smem, s));
+        return EWAH_OK;
+    }
+    if ((++c->epoch & 0xFFFFu) == 0) {   // 16-bit tags wrapped: clear stale states
+        HIPCHK(hipMemsetAsync(c->d_state, 0, c->state_cap * sizeof(TileState), s));
+        c->epoch = 1;
+    }
     HIPCHK(launch_query(q, g.d_table, c->d_ticket, c->epoch, g.d_err, s, pred ? pred->kind : (uint32_t)PRED_THRESHOLD));
     return EWAH_OK;
 }

@@ -244,3 +244,16 @@ def test_batched_matches_plain_and_oracle(G):
     assert E.device_errors() == 0
     for b in bms:
         b.release()
+
+
+def test_single_query_many_tiles(G):
+    """A single threshold query with more tiles than twice the resident workgroups runs as a
+    batch of one on the persistent kernel (staged tiles, scan, placement): every variant and
+    T from 0 to N + 1, fills spanning tiles, a ragged tail, and repeated calls on one stream
+    (device epochs of that path)."""
+    E = G.lib()
+    n_bits = 2100 * TW_ROWS + 777      # 2,101 tiles: above twice the resident workgroups of the kernel
+    keys = [D.key(8800, k) for k in range(5)]
+    streams = (D.bitmaps(D.IID, [0.002, 0.03], 0.0, n_bits, keys[:2]) +
+               D.bitmaps(D.MARKOV, [3000.0, 64.0, 20000.0], [9000.0, 900.0, 40000.0], n_bits, keys[2:]))
+    _check(G, streams, n_bits, range(0, len(streams) + 2), variants=_variants(E), label="many tiles")
