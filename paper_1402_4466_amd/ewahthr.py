@@ -205,18 +205,42 @@ def register(stream, n_bits: int) -> Bitmap:
     return register_many([stream], n_bits)[0]
 
 
+class Inputs:
+    """The inputs of a query marshalled once (the C array of handles), for callers that run
+    many queries over the same list; every query function takes it in place of a list."""
+
+    def __init__(self, bitmaps):
+        self.bitmaps = list(bitmaps)
+        self.n = len(self.bitmaps)
+        self.arr = (_vp * max(self.n, 1))(*[b.handle for b in self.bitmaps])
+
+    def __len__(self):
+        return self.n
+
+    def __getitem__(self, i):
+        return self.bitmaps[i]
+
+    def __iter__(self):
+        return iter(self.bitmaps)
+
+
+def _handles(bitmaps):
+    if isinstance(bitmaps, Inputs):
+        return bitmaps.arr, bitmaps.n
+    n = len(bitmaps)
+    return (_vp * max(n, 1))(*[b.handle for b in bitmaps]), n
+
+
 def threshold(bitmaps, T: int, out_words_ptr: int, out_cap: int, out_n_ptr: int, stream=None, variant: int = 0):
     """Enqueue one T-of-N query; outputs are device pointers (e.g. tensor.data_ptr())."""
-    n = len(bitmaps)
-    arr = (_vp * max(n, 1))(*[b.handle for b in bitmaps])
+    arr, n = _handles(bitmaps)
     _check(_threshold_v(arr, n, T, out_words_ptr, out_cap, out_n_ptr, variant, _stream_ptr(stream)), "threshold")
 
 
 def symmetric(bitmaps, f, out_words_ptr: int, out_cap: int, out_n_ptr: int, stream=None):
     """Enqueue one query of a symmetric function: output row i is f[c_i], c_i = number of inputs
     with row i set; f is a sequence of len(bitmaps) + 1 truth values (counts 0..N)."""
-    n = len(bitmaps)
-    arr = (_vp * max(n, 1))(*[b.handle for b in bitmaps])
+    arr, n = _handles(bitmaps)
     tab = (ctypes.c_uint8 * max(len(f), 1))(*[1 if v else 0 for v in f])
     _check(_symmetric(arr, n, tab, len(f), out_words_ptr, out_cap, out_n_ptr, _stream_ptr(stream)), "symmetric")
 
@@ -224,8 +248,7 @@ def symmetric(bitmaps, f, out_words_ptr: int, out_cap: int, out_n_ptr: int, stre
 def opt_threshold(bitmaps, K: int, out_words_ptr: int, out_cap: int, out_n_ptr: int, stream=None) -> int:
     """Largest T whose T-of-N result has at least K rows; its result is enqueued to the outputs.
     Returns T (the call waits for it)."""
-    n = len(bitmaps)
-    arr = (_vp * max(n, 1))(*[b.handle for b in bitmaps])
+    arr, n = _handles(bitmaps)
     t = _u32(0)
     _check(_opt_threshold(arr, n, K, out_words_ptr, out_cap, out_n_ptr, ctypes.byref(t), _stream_ptr(stream)),
            "opt_threshold")
@@ -234,8 +257,7 @@ def opt_threshold(bitmaps, K: int, out_words_ptr: int, out_cap: int, out_n_ptr: 
 
 def count_histogram(bitmaps, stream=None) -> np.ndarray:
     """hist[c] = rows set in exactly c of the inputs, c = 0..len(bitmaps) (the call waits)."""
-    n = len(bitmaps)
-    arr = (_vp * max(n, 1))(*[b.handle for b in bitmaps])
+    arr, n = _handles(bitmaps)
     hist = np.zeros(n + 1, dtype=np.uint64)
     _check(_count_histogram(arr, n, hist.ctypes.data, _stream_ptr(stream)), "count_histogram")
     return hist

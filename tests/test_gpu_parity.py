@@ -257,3 +257,23 @@ def test_single_query_many_tiles(G):
     streams = (D.bitmaps(D.IID, [0.002, 0.03], 0.0, n_bits, keys[:2]) +
                D.bitmaps(D.MARKOV, [3000.0, 64.0, 20000.0], [9000.0, 900.0, 40000.0], n_bits, keys[2:]))
     _check(G, streams, n_bits, range(0, len(streams) + 2), variants=_variants(E), label="many tiles")
+
+
+def test_prepared_inputs_match_lists(G):
+    """ewahthr.Inputs (handles marshalled once) gives the same results as a list of bitmaps
+    in every query function."""
+    E = G.lib()
+    n_bits = 3 * TW_ROWS + 17
+    streams = D.bitmaps(D.IID, [0.01, 0.2, 0.05, 0.3], 0.0, n_bits, [D.key(8900, k) for k in range(4)])
+    bms = G.register(streams, n_bits)
+    try:
+        ins = E.Inputs(bms)
+        for T in (1, 2, 4):
+            assert np.array_equal(G.gpu_threshold(ins, T), G.gpu_threshold(bms, T)), T
+        assert np.array_equal(E.count_histogram(ins), E.count_histogram(bms))
+        out, out_n, cap = G.alloc_out(n_bits, sum(len(s) for s in streams))
+        assert E.opt_threshold(ins, 5, out.data_ptr(), cap, out_n.data_ptr()) == \
+            E.opt_threshold(bms, 5, out.data_ptr(), cap, out_n.data_ptr())
+    finally:
+        for b in bms:
+            b.release()
