@@ -111,15 +111,18 @@ const uint64_t* ewah_device_words(const ewah_bitmap* b);
 uint64_t ewah_output_bound(uint64_t n_bits, uint64_t sum_input_words);
 
 /*
- * T-of-N threshold of in[0..n-1] (registered, equal n_bits, 1 <= n <= 4095;
- * n = 0 is EINVAL since the row count would be undefined).
+ * T-of-N threshold of in[0..n-1] (Section 2: row i of the result is set iff at
+ * least T of the n inputs have row i set; registered inputs, equal n_bits,
+ * 1 <= n <= 4095; n = 0 is EINVAL since the row count would be undefined).
  * Writes the canonical EWAH result to out_words_dev (device memory, caller
  * owned, out_cap words) and its length to *out_n_words_dev (device memory).
  * out_cap must be >= ewah_output_bound(n_bits, sum of input n_words), else
  * ENOSPC without any device work.  The work is enqueued on hip_stream (a
  * hipStream_t, NULL = default stream) and the call returns without waiting;
  * inputs must stay registered until it completes.  Concurrent calls on
- * different streams are allowed.
+ * different streams are allowed.  A query of more tiles than twice the
+ * resident workgroups runs as a batch of one on the persistent kernel (same
+ * result, still asynchronous).
  */
 ewah_status ewah_threshold(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
                            uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream);
@@ -210,6 +213,9 @@ typedef struct {
 typedef struct ewah_batch ewah_batch;
 
 /*
+ * Batches of threshold queries over one pool of bitmaps, as in the workloads
+ * of Section 7.3 (thousands of queries, each over N bitmaps of one dataset),
+ * each query with the meaning of ewah_threshold (Section 2).
  * Plans a batch: uploads the query table (inputs as pool indices, thresholds,
  * output pointers, variants) and, with use_graph, captures the launch into a
  * HIP graph.  pool[] must stay registered while the batch exists.  All pool
