@@ -60,13 +60,14 @@ struct Ctx {                       // per-stream query state
     unsigned long long* d_acc = nullptr;   // opt-threshold: largest count / output row count / histogram
     unsigned long long* h_acc = nullptr;   // pinned copy (MAXN + 1 values)
     // single threshold queries of many tiles run through the persistent batched kernel
-    // (staged tiles, scan, placement) as a batch of one: its own tile states (tagged with
-    // the device epoch at work1[1]), staging area and item-to-query map (all zeros)
+    // (staged tiles, scan, placement) as a batch of one: its own tile states, staging area
+    // and item-to-query map (all zeros); its work words (epoch, item counters) are
+    // uploaded with the input slots, the epoch counted here
     TileState* d_state1 = nullptr;
     uint64_t* d_stage1 = nullptr;
     uint32_t* d_tq1 = nullptr;
     size_t tiles1_cap = 0;
-    uint32_t* d_work1 = nullptr;
+    uint32_t epoch1 = 0;
 };
 
 struct Lib {
@@ -284,10 +285,6 @@ ewah_status ctx_reserve(Ctx& c, hipStream_t s, size_t n_ids, size_t tiles) {
 
 // Buffers of the one-query batched run for queries of up to `tiles` tiles.
 ewah_status ctx_reserve_batched(Ctx& c, hipStream_t s, size_t tiles) {
-    if (!c.d_work1) {
-        HIPCHK(hipMalloc(&c.d_work1, WORK_WORDS * 4));
-        HIPCHK(hipMemset(c.d_work1, 0, WORK_WORDS * 4));
-    }
     if (tiles > c.tiles1_cap) {
         HIPCHK(hipStreamSynchronize(s));   // earlier runs on this stream may still use the old buffers
         if (c.d_state1) HIPCHK(hipFree(c.d_state1));
@@ -302,6 +299,7 @@ ewah_status ctx_reserve_batched(Ctx& c, hipStream_t s, size_t tiles) {
         HIPCHK(hipMalloc(&c.d_tq1, cap * 4));
         HIPCHK(hipMemset(c.d_tq1, 0, cap * 4));
         c.tiles1_cap = cap;
+        c.epoch1 = 0;   // fresh states hold tag 0, which no epoch takes
     }
     return EWAH_OK;
 }
@@ -518,15 +516,17 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
     // A threshold query with more tiles than twice the resident workgroups runs as a
     // batch of one on the persistent kernel: its tiles are taken in turn from per-XCD
     // ranges and placed by a scan, instead of one workgroup per tile chained by
-    // look-back.  Its query record and item range {0, tiles} are staged after the slots.
+    // look-back.  Its query record, item range {0, tiles} and work words (epoch and
+    // cleared item counters, 64-byte aligned) are staged after the slots.
     const size_t smem = tile_smem_bytes(n);
     const uint32_t resident = batch_resident(smem);
     const bool batched = !pred && tiles >= 2u * resident;
-    size_t q_off = 0, qt_off = 0;
+    size_t q_off = 0, qt_off = 0, w_off = 0;
     if (batched) {
         q_off = (n_stage + 1) & ~(size_t)1;          // 8-byte aligned
         qt_off = q_off + sizeof(QueryDev) / 4;
-        n_stage = qt_off + 2;
+        w_off = (qt_off + 2 + 15) & ~(size_t)15;     // 64-byte aligned
+        n_stage = w_off + WORK_WORDS;
     }
     Ctx* c = nullptr;
     st = get_ctx(s, &c);
@@ -558,13 +558,18 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
         std::memcpy(c->h_ids + q_off, &q, sizeof(QueryDev));
         c->h_ids[qt_off] = 0u;
         c->h_ids[qt_off + 1] = tiles;
+        uint32_t e = c->epoch1 + 1u;   // 16-bit state tags: skip tag 0
+        if ((e & 0xFFFFu) == 0) e += 1u;
+        c->epoch1 = e;
+        std::memset(c->h_ids + w_off, 0, WORK_WORDS * 4);
+        c->h_ids[w_off + 1] = e;
     }
     HIPCHK(hipMemcpyAsync(c->d_ids, c->h_ids, n_stage * 4, hipMemcpyHostToDevice, s));
     HIPCHK(hipEventRecord(c->ev, s));
     if (batched) {
-        HIPCHK(launch_bump(c->d_work1, s));
+        uint32_t* work = c->d_ids + w_off;
         HIPCHK(launch_batch((const QueryDev*)(c->d_ids + q_off), c->d_ids + qt_off, c->d_tq1, 1u, tiles, g.d_table,
-                            c->d_work1, c->d_work1 + 1, g.d_err, resident, smem, s));
+                            work, work + 1, g.d_err, resident, smem, s));
         return EWAH_OK;
     }
     if ((++c->epoch & 0xFFFFu) == 0) {   // 16-bit tags wrapped: clear stale states
