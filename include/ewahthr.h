@@ -120,7 +120,7 @@ uint64_t ewah_output_bound(uint64_t n_bits, uint64_t sum_input_words);
  * ENOSPC without any device work.  The work is enqueued on hip_stream (a
  * hipStream_t, NULL = default stream) and the call returns without waiting;
  * inputs must stay registered until it completes.  Concurrent calls on
- * different streams are allowed.  A query of more tiles than twice the
+ * different streams are allowed.  A query of more tiles than there are
  * resident workgroups runs as a batch of one on the persistent kernel (same
  * result, still asynchronous).
  */

@@ -513,14 +513,14 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
     // staging: the n slots, then (8-byte aligned) the predicate record
     const size_t pred_off = ((size_t)n + 1) & ~(size_t)1;
     size_t n_stage = pred ? pred_off + sizeof(PredDev) / 4 : n;
-    // A threshold query with more tiles than twice the resident workgroups runs as a
+    // A threshold query with more tiles than resident workgroups runs as a
     // batch of one on the persistent kernel: its tiles are taken in turn from per-XCD
     // ranges and placed by a scan, instead of one workgroup per tile chained by
     // look-back.  Its query record, item range {0, tiles} and work words (epoch and
     // cleared item counters, 64-byte aligned) are staged after the slots.
     const size_t smem = tile_smem_bytes(n);
     const uint32_t resident = batch_resident(smem);
-    const bool batched = !pred && tiles >= 2u * resident;
+    const bool batched = !pred && tiles > resident;
     size_t q_off = 0, qt_off = 0, w_off = 0;
     if (batched) {
         q_off = (n_stage + 1) & ~(size_t)1;          // 8-byte aligned

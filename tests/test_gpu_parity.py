@@ -247,12 +247,12 @@ def test_batched_matches_plain_and_oracle(G):
 
 
 def test_single_query_many_tiles(G):
-    """A single threshold query with more tiles than twice the resident workgroups runs as a
+    """A single threshold query with more tiles than there are resident workgroups runs as a
     batch of one on the persistent kernel (staged tiles, scan, placement): every variant and
     T from 0 to N + 1, fills spanning tiles, a ragged tail, and repeated calls on one stream
     (device epochs of that path)."""
     E = G.lib()
-    n_bits = 2100 * TW_ROWS + 777      # 2,101 tiles: above twice the resident workgroups of the kernel
+    n_bits = 2100 * TW_ROWS + 777      # 2,101 tiles: above the resident workgroups of the kernel
     keys = [D.key(8800, k) for k in range(5)]
     streams = (D.bitmaps(D.IID, [0.002, 0.03], 0.0, n_bits, keys[:2]) +
                D.bitmaps(D.MARKOV, [3000.0, 64.0, 20000.0], [9000.0, 900.0, 40000.0], n_bits, keys[2:]))
@@ -277,3 +277,14 @@ def test_prepared_inputs_match_lists(G):
     finally:
         for b in bms:
             b.release()
+
+
+def test_single_query_around_the_switch(G):
+    """512 tiles (one per resident workgroup: look-back kernel) and 513 tiles (batch of one)."""
+    E = G.lib()
+    for tiles in (512, 513):
+        n_bits = (tiles - 1) * TW_ROWS + 4097
+        streams = D.bitmaps(D.MARKOV, 32.0, 512.0, n_bits, [D.key(8810 + tiles, k) for k in range(6)])
+        _check(G, streams, n_bits, (0, 1, 2, 4, 7), variants=(0, E.variant_code(False, 0, 0),
+                                                            E.variant_code(False, 8, 8, looped=True)),
+               label=f"{tiles} tiles")
