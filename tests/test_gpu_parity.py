@@ -288,3 +288,79 @@ def test_single_query_around_the_switch(G):
         _check(G, streams, n_bits, (0, 1, 2, 4, 7), variants=(0, E.variant_code(False, 0, 0),
                                                             E.variant_code(False, 8, 8, looped=True)),
                label=f"{tiles} tiles")
+
+
+def _bits_to_stream(bits):
+    """Row i = character / element i (the walk-throughs list rows left to right)."""
+    w = 0
+    for i, b in enumerate(bits):
+        w |= int(b) << i
+    return literal_stream([w])
+
+
+def _stream_rows(words, r):
+    d = O.decode(words, r)
+    return [int((int(d[i // 64]) >> (i % 64)) & 1) for i in range(r)]
+
+
+def test_golden_walkthroughs_on_the_gpu(G):
+    """The paper's printed walk-throughs through the GPU path: Looped (Section 6.2) at T = 1
+    and 2, BSTM (Section 5.3.1) at T = 2 and its slices A1 (odd count) and A2 (count in
+    [2, 3]) as symmetric functions, the Hamming-weight figure's slices and histogram, and the
+    Section 2 example as threshold and opt-threshold; every threshold under every variant."""
+    E = G.lib()
+    lp = golden("looped_walkthrough.json")
+    bm = golden("bstm_walkthrough.json")
+    hw = golden("hamming_weight.json")
+    fx = golden("formulation_example.json")
+
+    def run(bitmaps, r, check):
+        bms = G.register([_bits_to_stream(b) for b in bitmaps], r)
+        try:
+            check(bms)
+        finally:
+            for b in bms:
+                b.release()
+
+    def thr(bms, T, v=0):
+        return _stream_rows(G.gpu_threshold(bms, T, variant=v), bms[0].n_bits)
+
+    def sym(bms, f):
+        out, out_n, cap = G.alloc_out(bms[0].n_bits, sum(b.n_words for b in bms))
+        E.symmetric(bms, f, out.data_ptr(), cap, out_n.data_ptr())
+        return _stream_rows(G.fetch(out, out_n), bms[0].n_bits)
+
+    as_list = lambda s: [int(c) for c in s]
+
+    def looped(bms):
+        for v in _variants(E):
+            assert thr(bms, 1, v) == as_list(lp["C1"]) and thr(bms, 2, v) == as_list(lp["C2"]), v
+    run(lp["bitmaps"], lp["r"], looped)
+
+    def bstm(bms):
+        for v in _variants(E):
+            assert thr(bms, bm["T"], v) == as_list(bm["expected"]), v
+        assert sym(bms, [0, 1, 0, 1]) == as_list(bm["A1"])
+        assert sym(bms, [0, 0, 1, 1]) == as_list(bm["A2"])
+    run(bm["bitmaps"], bm["r"], bstm)
+
+    cols = [[row[k] for row in hw["rows"]] for k in range(3)]   # bitmap k = column k of the rows
+
+    def hamming(bms):
+        assert sym(bms, [0, 1, 0, 1]) == hw["A1"] and sym(bms, [0, 0, 1, 1]) == hw["A2"]
+        want = [sum(1 for w in hw["weight"] if w == c) for c in range(4)]
+        assert E.count_histogram(bms).tolist() == want
+    run(cols, len(hw["rows"]), hamming)
+
+    r = fx["r"]
+    sets = [[1 if i in s else 0 for i in range(r)] for s in fx["sets"]]
+
+    def formulation(bms):
+        for T, rows in fx["expected"].items():
+            want = [1 if i in rows else 0 for i in range(r)]
+            for v in _variants(E):
+                assert thr(bms, int(T), v) == want, (T, v)
+        out, out_n, cap = G.alloc_out(r, sum(b.n_words for b in bms))
+        assert E.opt_threshold(bms, 1, out.data_ptr(), cap, out_n.data_ptr()) == 2
+        assert _stream_rows(G.fetch(out, out_n), r) == [1 if i in fx["expected"]["2"] else 0 for i in range(r)]
+    run(sets, r, formulation)
