@@ -280,11 +280,14 @@ def test_prepared_inputs_match_lists(G):
 
 
 def test_single_query_around_the_switch(G):
-    """512 tiles (one per resident workgroup: look-back kernel) and 513 tiles (batch of one)."""
+    """512 tiles (one per resident workgroup: look-back kernel) and 513 tiles (batch of one), on
+    non-canonical input streams."""
     E = G.lib()
     for tiles in (512, 513):
         n_bits = (tiles - 1) * TW_ROWS + 4097
-        streams = D.bitmaps(D.MARKOV, 32.0, 512.0, n_bits, [D.key(8810 + tiles, k) for k in range(6)])
+        # non-canonical but well-formed streams (split runs, empty markers, fill-valued literals)
+        streams = D.bitmaps(D.MARKOV, 32.0, 512.0, n_bits, [D.key(8810 + tiles, k) for k in range(6)],
+                            noncanon=True)
         _check(G, streams, n_bits, (0, 1, 2, 4, 7), variants=(0, E.variant_code(False, 0, 0),
                                                             E.variant_code(False, 8, 8, looped=True)),
                label=f"{tiles} tiles")
