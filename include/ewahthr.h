@@ -170,7 +170,8 @@ ewah_status ewah_opt_threshold(const ewah_bitmap* const* in, uint32_t n, uint64_
  */
 ewah_status ewah_count_histogram(const ewah_bitmap* const* in, uint32_t n, uint64_t* hist, void* hip_stream);
 
-/* As ewah_threshold with an explicit kernel variant (ewah_variant_code); the result is identical. */
+/* As ewah_threshold with an explicit kernel variant (ewah_variant_code); the result is identical.
+ * variant = 0 takes the default: the unary counter at T <= 2, else ewah_default_variant(). */
 ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
                              uint64_t out_cap, uint64_t* out_n_words_dev, uint32_t variant, void* hip_stream);
 

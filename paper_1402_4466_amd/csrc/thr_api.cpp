@@ -549,7 +549,11 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
     q.U = U;
     q.tiles = tiles;
     q.tail_bits = (uint32_t)(n_bits % 64);
-    q.variant = variant ? variant : ewah_default_variant();
+    // default variant of a single threshold query: the unary counter at T <= 2 (an add
+    // stops within two levels; measured faster there), else the library default
+    const uint32_t T_eff = pred ? pred->tz : T;
+    q.variant = variant ? variant
+                        : ((!pred && T_eff >= 1u && T_eff <= 2u) ? var_make(false, 8, 8, true) : ewah_default_variant());
     q.pd = pred ? (const PredDev*)(c->d_ids + pred_off) : nullptr;
     HIPCHK(hipEventSynchronize(c->ev));   // previous upload from the staging buffer is done
     for (uint32_t i = 0; i < n; ++i) c->h_ids[i] = in[i]->slot;
