@@ -16,7 +16,7 @@ segment may be before it is split across a wavefront).  Three selectors share on
                 estimate (hybrid H, Section 8.2);
   FixedSelector one arm for every query.
 
-Exhaustive timing (the oracle selector H_opt of Section 8.2) is the judge of
+Exhaustive timing (the oracle selector H_opt of Section 8.2) measures
 their regret; it lives in train_selector.py.
 """
 from __future__ import annotations
