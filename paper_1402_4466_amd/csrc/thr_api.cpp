@@ -4,11 +4,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/ewahthr.h"
@@ -370,16 +373,41 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
     if (!v || !out) return fail(EWAH_EINVAL, "null argument");
     std::vector<Built> built(count);
     std::vector<std::vector<uint64_t>> host(count);
+    std::vector<const uint64_t*> src(count);
     for (uint32_t i = 0; i < count; ++i) {
         if (v[i].n_words && !v[i].words) return fail(EWAH_EINVAL, "null words pointer");
-        const uint64_t* w = v[i].words;
+        src[i] = v[i].words;
         if (on_device && v[i].n_words) {
             host[i].resize(v[i].n_words);
             HIPCHK(hipMemcpy(host[i].data(), v[i].words, v[i].n_words * 8, hipMemcpyDeviceToHost));
-            w = host[i].data();
+            src[i] = host[i].data();
         }
-        st = build_index(w, v[i].n_words, v[i].n_bits, built[i]);
-        if (st) return fail(st, "bitmap " + std::to_string(i) + ": " + g_err);
+    }
+    // validation and index building, one bitmap at a time on up to 16 host threads; the
+    // first failing bitmap (lowest index) is reported
+    {
+        const uint32_t nt = std::max(1u, std::min({16u, std::thread::hardware_concurrency(), count}));
+        std::atomic<uint32_t> next{0};
+        std::mutex mu;
+        uint32_t bad = count;
+        ewah_status bad_st = EWAH_OK;
+        std::string bad_msg;
+        auto work = [&]() {
+            for (;;) {
+                const uint32_t i = next.fetch_add(1);
+                if (i >= count) return;
+                const ewah_status e = build_index(src[i], v[i].n_words, v[i].n_bits, built[i]);
+                if (e) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    if (i < bad) { bad = i; bad_st = e; bad_msg = g_err; }   // g_err of this thread
+                }
+            }
+        };
+        std::vector<std::thread> pool;
+        for (uint32_t k = 1; k < nt; ++k) pool.emplace_back(work);
+        work();
+        for (auto& th : pool) th.join();
+        if (bad < count) return fail(bad_st, "bitmap " + std::to_string(bad) + ": " + bad_msg);
     }
     // one device arena per call; per bitmap [words padded to CHUNK, plus CHUNK zero words |
     // skip index | locator | 4-word-group presence | word presence], each part 256-byte aligned.  The image is assembled on the host

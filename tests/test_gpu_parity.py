@@ -179,6 +179,13 @@ def test_errors_and_bounds(G):
     with pytest.raises(E.EwahError) as e:
         E.register_many([np.array([marker(0, 1, 5), 1, 2], dtype=np.uint64)], r)
     assert e.value.code == E.EFORMAT
+    # many streams built in parallel: the lowest failing index is the one reported
+    many = [good] * 40
+    many[31] = np.array([marker(0, 1, 5), 1, 2], dtype=np.uint64)   # ends inside its literal run
+    many[17] = np.array([marker(0, 3, 0)], dtype=np.uint64)          # covers 3 of 16 words
+    with pytest.raises(E.EwahError) as e:
+        E.register_many(many, r)
+    assert e.value.code == E.EFORMAT and "bitmap 17:" in str(e.value), str(e.value)
     bms = G.register([good], r)
     out, out_n, cap = G.alloc_out(r, 10)
     with pytest.raises(E.EwahError) as e:
