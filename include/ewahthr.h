@@ -89,7 +89,9 @@ const char* ewah_last_error(void);
  */
 ewah_status ewah_register(const ewah_view* v, int on_device, ewah_bitmap** out);
 
-/* Same for count bitmaps at once (one device allocation); out[i] for v[i]. */
+/* Same for count bitmaps at once (one device allocation; the indexes are built on
+ * up to 16 host threads); out[i] for v[i].  On failure nothing is registered and
+ * the error names the lowest failing index. */
 ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device, ewah_bitmap** out);
 
 /* Frees a registered bitmap.  No query using it may still be in flight. */
