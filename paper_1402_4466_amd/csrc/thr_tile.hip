@@ -345,7 +345,7 @@ __device__ Agg lookback(EWT_GLOBAL TileState* st, int t, uint32_t epoch, uint32_
 
 // Cooperative windows taken by one wavefront at a time: all their loads are
 // issued before any of them is decoded.
-constexpr int WIN_BATCH = 8;
+constexpr int WIN_BATCH = 7;
 
 #ifdef EWT_PHASE_TIMING
 // Debug builds only: per-tile timestamps of the phase boundaries.
