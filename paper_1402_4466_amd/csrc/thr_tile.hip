@@ -672,13 +672,14 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         Tz = Rmax + 1u;   // groups that cannot exceed the running maximum add nothing
     }
     // per-group bounds: counted only when fewer than T inputs touch every group and
-    // T is above 9/10 of the mean bound (else few groups, if any, fall below T)
+    // T is above 11/10 of the mean bound (else few groups fall below T and the count costs more
+    // than it saves)
     PMask pm;
     pm.w = misc + M_PR;
     pm.sh = gsh;
     pm.ng = ng;
     pm.on = false;
-    if (mode == 0 && misc[M_DFULL] < Tz && 10ull * Tz * ngv > 9ull * misc[M_PSUM]) {
+    if (mode == 0 && misc[M_DFULL] < Tz && 10ull * Tz * ngv > 11ull * misc[M_PSUM]) {
         if (fine) count_quads<4>(prs, PCAP_FINE, min(N, PCAP_FINE), gcnt);
         else count_quads<16>(prs, PCAP_COARSE, min(N, PCAP_COARSE), gcnt);
         if (N > pcap) {   // the rest of very wide queries (4-word groups): wavefront ballots
