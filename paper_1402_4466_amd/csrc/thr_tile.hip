@@ -1357,9 +1357,10 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_max_kernel(QueryDev q, con
 // neighbouring tiles of a query, which share the compressed chunk at their boundary,
 // are read through one L2.  A workgroup takes the next item of its own range from
 // that range's counter and, once the range is used up, items of the other ranges in
-// turn.  qtile[i] = first item of query i (qtile[nq] = total).
+// turn.  qtile[i] = first item of query i (qtile[nq] = total); tq[i] = query of item i.
 __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
-                                                          uint32_t nq, const BitmapDev* __restrict__ table,
+                                                          const uint32_t* __restrict__ tq, uint32_t nq,
+                                                          const BitmapDev* __restrict__ table,
                                                           uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_item, s_q;
@@ -1377,17 +1378,8 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __r
                 const uint32_t c = atomicAdd(&work[WORK_CTR + WORK_STRIDE * x], 1u);
                 if (c < hi - lo) { it = lo + c; break; }
             }
-            uint32_t qi = 0;
-            if (it < total) {
-                uint32_t lo = 0, hi = nq - 1;
-                while (lo < hi) {
-                    uint32_t mid = (lo + hi + 1) >> 1;
-                    if (qtile[mid] <= it) lo = mid; else hi = mid - 1;
-                }
-                qi = lo;
-            }
             s_item = it;
-            s_q = qi;
+            s_q = (it < total && nq > 1u) ? tq[it] : 0u;   // query of the item (one load; a batch of one needs none)
         }
         __syncthreads();
         // uniform: the query record is then read into scalar registers
@@ -1472,7 +1464,7 @@ hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* tic
 hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_t* tq, uint32_t nq, uint32_t total,
                         const BitmapDev* table, uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid,
                         size_t smem, hipStream_t s) {
-    hipLaunchKernelGGL(thr_batch_kernel, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, nq, table, work, epoch_ptr, err);
+    hipLaunchKernelGGL(thr_batch_kernel, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work, epoch_ptr, err);
     hipLaunchKernelGGL(scan_batch_kernel, dim3(nq), dim3(SCAN_THREADS), 0, s, qs, epoch_ptr, err);
     hipLaunchKernelGGL(place_batch_kernel, dim3((total + 3) / 4), dim3(256), 0, s, qs, qtile, tq, total, epoch_ptr, err);
     return hipGetLastError();
