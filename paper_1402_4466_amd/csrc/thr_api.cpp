@@ -775,6 +775,7 @@ struct ewah_batch {
     QueryDev* d_qs = nullptr;
     uint32_t* d_qtile = nullptr;
     uint32_t* d_ids = nullptr;
+    BitmapDev* d_bms = nullptr;    // every query's input descriptors, in the order of d_ids
     TileState* d_state = nullptr;
     uint64_t* d_stage = nullptr;   // STAGE_WORDS per tile of every query
     uint32_t* d_tq = nullptr;      // query of every (query, tile) item
@@ -855,6 +856,12 @@ ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, con
     if ((uint64_t)qtile[nq] * 1 >= (1ull << 31)) return fail(EWAH_EINVAL, "too many tiles in one batch");
     HIPCHK(hipMalloc(&b->d_ids, ids.size() * 4));
     HIPCHK(hipMemcpy(b->d_ids, ids.data(), ids.size() * 4, hipMemcpyHostToDevice));
+    {
+        std::vector<BitmapDev> bmsv(ids.size());
+        for (size_t k = 0; k < ids.size(); ++k) bmsv[k] = g.table[ids[k]];
+        HIPCHK(hipMalloc(&b->d_bms, std::max<size_t>(bmsv.size(), 1) * sizeof(BitmapDev)));
+        HIPCHK(hipMemcpy(b->d_bms, bmsv.data(), bmsv.size() * sizeof(BitmapDev), hipMemcpyHostToDevice));
+    }
     HIPCHK(hipMalloc(&b->d_state, (size_t)qtile[nq] * sizeof(TileState)));
     HIPCHK(hipMemset(b->d_state, 0, (size_t)qtile[nq] * sizeof(TileState)));
     if (hipMalloc(&b->d_stage, (size_t)qtile[nq] * STAGE_WORDS * sizeof(uint64_t)) != hipSuccess)
@@ -877,6 +884,7 @@ ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, con
     for (uint32_t i = 0; i < nq; ++i) {
         QueryDev& d = b->h_qs[i];
         d.ids = b->d_ids + id_off[i];
+        d.bms = b->d_bms + id_off[i];
         d.out = q[i].out_words_dev;
         d.out_n = q[i].out_n_words_dev;
         d.state = b->d_state + qtile[i];
@@ -938,6 +946,7 @@ void ewah_batch_free(ewah_batch* b) {
     (void)hipFree(b->d_qs);
     (void)hipFree(b->d_qtile);
     (void)hipFree(b->d_ids);
+    (void)hipFree(b->d_bms);
     (void)hipFree(b->d_state);
     (void)hipFree(b->d_stage);
     (void)hipFree(b->d_tq);

@@ -142,7 +142,9 @@ struct QueryDev {         // 88 bytes
     uint32_t tail_bits;   // n_bits % 64
     uint32_t variant;     // VAR_* flags
     const PredDev* pd;    // null: count >= T
+    const BitmapDev* bms; // batches: the N inputs' descriptors in query order (null: table[ids[k]])
 };
+static_assert(sizeof(QueryDev) % 8 == 0, "query records are copied as 64-bit words");
 
 // Variant flags (kernel strategy knobs; results never depend on them).
 enum : uint32_t {

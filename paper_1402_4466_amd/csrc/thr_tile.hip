@@ -529,6 +529,12 @@ static_assert(PCAP_FINE / 4 < 256u && PCAP_COARSE / 16 < 256u, "byte counters");
 // STAGED: the tile writes its words to the staging area and publishes its
 // aggregate (a placement pass finishes the output); otherwise it finds the prefix
 // over earlier tiles by look-back and writes its words in place.
+// Descriptor of input k of a query: from the query's own copy (batches: one coalesced
+// read) or through the slot table.
+__device__ __forceinline__ BitmapDev input_of(const QueryDev& q, const BitmapDev* __restrict__ table, uint32_t k) {
+    return q.bms ? gp(q.bms)[k] : gp(table)[gp(q.ids)[k]];
+}
+
 static_assert((MAXN + 1u) * 4u <= (uint32_t)WCAP * 16u, "count histogram must fit in the window list");
 
 template <bool STAGED, bool GENERAL = false, bool MAXC = false, bool LOOPED = false, bool HIST = false>
@@ -595,7 +601,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             bool onefull = false, nonzero = false;
             uint32_t np = 0;
             if (k < N) {
-                const BitmapDev B = gp(table)[gp(q.ids)[k]];
+                const BitmapDev B = input_of(q, table, k);
                 const uint4* src = (fine ? B.pres1 : B.pres) + (size_t)t * pv;
 #pragma unroll
                 for (int v = 0; v < PV_FINE; ++v) {
@@ -690,7 +696,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
 #pragma unroll
                 for (int v = 0; v < PV_COARSE; ++v) pr[v] = make_uint4(0u, 0u, 0u, 0u);
                 if (k < N) {
-                    const uint4* src = gp(gp(table)[gp(q.ids)[k]].pres) + (size_t)t * PV_COARSE;
+                    const uint4* src = gp(input_of(q, table, k).pres) + (size_t)t * PV_COARSE;
 #pragma unroll
                     for (int v = 0; v < PV_COARSE; ++v) pr[v] = src[v];
                 }
@@ -722,7 +728,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             const uint4* dp = nullptr;
             if (k < N) {
                 BitmapDev B = B0;
-                if (kb != 0) B = gp(table)[gp(q.ids)[k]];
+                if (kb != 0) B = input_of(q, table, k);
                 s = (kb == 0) ? seg : locate(B, t, tS, tE, tiles);
                 wp = B.words;
                 dp = B.desc;
@@ -754,7 +760,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                 if (W0 > 0) {   // later rounds (long tiles): the segment is located again
                     const uint32_t j0 = max(off, W0), j1 = min(off + nlw + nww, W0 + nr);
                     if (j0 < j1) {
-                        const BitmapDev B = gp(table)[gp(q.ids)[k]];
+                        const BitmapDev B = input_of(q, table, k);
                         const Seg s2 = locate(B, t, tS, tE, tiles);
                         for (uint32_t j = j0; j < j1; ++j)
                             win[j - W0] = window_entry(B.words, B.desc, s2.bs, s2.be, s2.a_lit, s2.cnt, s2.la, nlw, j - off);
