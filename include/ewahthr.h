@@ -105,10 +105,14 @@ const uint64_t* ewah_device_words(const ewah_bitmap* b);
 /*
  * Upper bound on the canonical output length in words for inputs of
  * sum_input_words words in total over n_bits rows: 0 if n_bits = 0, else
- * min(U + 1, sum_input_words + 2).  Every output word is charged to a distinct
- * input word at the same position (an output dirty word needs an input dirty
- * word there; an output marker needs an input dirty word or an input run
- * starting there), plus the head marker and one dirty word for N = 0.
+ * min(U + 1, sum_input_words + 1).  U + 1: one word per position plus the
+ * head marker.  sum + 1: every output word at a position p > 0 is charged to a
+ * distinct input word at p (an output dirty word needs an input dirty word
+ * there, since positions where every input is a fill give a fill; an output
+ * marker needs an input dirty word or an input marker whose run starts there),
+ * and the words at position 0 to the first marker and dirty word of an input,
+ * plus one word of slack.  Queries need 1 <= N, so the N = 0 result (all ones
+ * or all zeros over the rows) never needs a bound.
  */
 uint64_t ewah_output_bound(uint64_t n_bits, uint64_t sum_input_words);
 

@@ -357,7 +357,7 @@ uint32_t ewah_num_cus(void) { return g.n_cu; }
 uint64_t ewah_output_bound(uint64_t n_bits, uint64_t sum_input_words) {
     uint64_t U = (n_bits + 63) / 64;
     if (U == 0) return 0;
-    return std::min<uint64_t>(U + 1, sum_input_words + 2);
+    return std::min<uint64_t>(U + 1, sum_input_words + 1);
 }
 
 uint32_t ewah_variant_code(int dense, uint32_t walk, uint32_t litwalk) { return var_make(dense != 0, walk, litwalk); }
@@ -836,6 +836,7 @@ ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, con
     std::vector<uint32_t> qtile(nq + 1, 0);
     std::vector<size_t> id_off(nq);
     uint32_t maxN = 1;
+    uint64_t items = 0;   // (query, tile) items, summed in 64 bits and checked before anything is allocated
     for (uint32_t i = 0; i < nq; ++i) {
         if (q[i].n == 0 || q[i].n > MAXN || !q[i].idx || !q[i].out_n_words_dev || !q[i].out_words_dev)
             return fail(EWAH_EINVAL, "query " + std::to_string(i) + ": bad arguments");
@@ -851,9 +852,11 @@ ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, con
         if (q[i].out_cap < bound)
             return fail(EWAH_ENOSPC, "query " + std::to_string(i) + ": out_cap below bound " + std::to_string(bound));
         maxN = std::max(maxN, q[i].n);
-        qtile[i + 1] = qtile[i] + tiles;
+        items += tiles;
+        if (items >= (1ull << 31))
+            return fail(EWAH_EINVAL, "too many tiles in one batch (at most 2^31 - 1 (query, tile) items)");
+        qtile[i + 1] = (uint32_t)items;
     }
-    if ((uint64_t)qtile[nq] * 1 >= (1ull << 31)) return fail(EWAH_EINVAL, "too many tiles in one batch");
     HIPCHK(hipMalloc(&b->d_ids, ids.size() * 4));
     HIPCHK(hipMemcpy(b->d_ids, ids.data(), ids.size() * 4, hipMemcpyHostToDevice));
     {

@@ -356,7 +356,7 @@ __device__ uint64_t* ewt_phase_buf;
 #endif
 
 // Misc LDS slots.
-enum { M_NDENSE = 1, M_PSUM = 2, M_ONEFULL = 4, M_NONZERO = 5, M_DFULL = 6, M_MAX = 7, M_TMP = 8, M_X = 32, M_TOT = 40, M_PR = 64 };
+enum { M_NDENSE = 1, M_PSUM = 2, M_ONEFULL = 4, M_NONZERO = 5, M_DFULL = 6, M_MAX = 7, M_TMP = 8, M_RMAX = 24, M_X = 32, M_TOT = 40, M_PR = 64 };
 static_assert(M_PR + PMW_MAX <= MISC_WORDS, "misc slots");
 
 // Presence group of tile-relative position rel is pruned (positions outside the
@@ -569,6 +569,11 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     uint32_t* gcnt = (uint32_t*)dense;
     if (tid < 8) misc[tid] = 0;
     if (tid < PMW_MAX) misc[M_PR + tid] = 0;
+    // largest count: one read of the running maximum for the whole workgroup (other
+    // workgroups raise it meanwhile; every wavefront must take the same early exit)
+    if constexpr (MAXC && !HIST) {
+        if (tid == 0) misc[M_RMAX] = (uint32_t)__hip_atomic_load(q.pd->acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __syncthreads();
 
     // ---- classify / prune (RBMrg on EWAH, cases 1 and 2, per tile)
@@ -582,8 +587,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     if constexpr (HIST) trivial = false;
     if constexpr (MAXC && !HIST) {
         trivial = false;
-        Rmax = (uint32_t)__builtin_amdgcn_readfirstlane(
-            (int)(uint32_t)__hip_atomic_load(q.pd->acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        Rmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)misc[M_RMAX]);   // the workgroup's one read
     }
     Seg seg;
     BitmapDev B0;

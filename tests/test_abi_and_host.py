@@ -52,7 +52,7 @@ def test_output_bound_definition_and_true_sizes(E):
     assert E.output_bound(0, 10) == 0
     assert E.output_bound(64, 1) == 2
     assert E.output_bound(64 * 100, 10**9) == 101
-    assert E.output_bound(64 * 100, 3) == 5
+    assert E.output_bound(64 * 100, 3) == 4
     rng = np.random.default_rng(7)
     for case in range(40):
         n_bits = int(rng.integers(1, 5000))

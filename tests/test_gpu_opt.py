@@ -146,3 +146,27 @@ def test_count_histogram_full_config2_and_errors(G):
         for b in bms:
             b.release()
     assert E.device_errors() == 0
+
+
+def test_largest_count_many_tiles(G):
+    """The largest-count pass reads the running maximum once per workgroup, so every
+    wavefront of a tile takes the same early exit while other tiles raise the maximum;
+    many tiles of uneven counts (word and 4-word bounds) make the maximum move during the
+    launch."""
+    E = G.lib()
+    for n, seed in ((48, 951), (300, 952)):
+        n_bits = 40 * TW_ROWS + 17
+        rng = np.random.default_rng(seed)
+        dens = rng.uniform(0.0005, 0.05, n)
+        streams = D.bitmaps(D.MARKOV, 32.0, 32.0 * (1.0 - dens) / dens, n_bits, [D.key(seed, k) for k in range(n)])
+        bms = G.register(streams, n_bits)
+        try:
+            want_T, want = O.opt_threshold(streams, n_bits, 1)
+            for rep in range(3):
+                T, got = _gpu_opt(G, bms, 1)
+                print(f"largest count N={n} rep {rep}: T={T}", flush=True)
+                assert T == want_T and np.array_equal(got, want), (n, rep)
+        finally:
+            for b in bms:
+                b.release()
+    assert E.device_errors() == 0

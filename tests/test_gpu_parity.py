@@ -198,7 +198,7 @@ def test_errors_and_bounds(G):
     for b in bms + other:
         b.release()
     assert E.output_bound(0, 5) == 0
-    assert E.output_bound(64 * 10, 3) == 5
+    assert E.output_bound(64 * 10, 3) == 4
     assert E.output_bound(64 * 10, 100) == 11
 
 
