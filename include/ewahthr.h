@@ -176,6 +176,22 @@ ewah_status ewah_opt_threshold(const ewah_bitmap* const* in, uint32_t n, uint64_
  */
 ewah_status ewah_count_histogram(const ewah_bitmap* const* in, uint32_t n, uint64_t* hist, void* hip_stream);
 
+/*
+ * As ewah_threshold, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * call allocates nothing.  Its per-call device state (tile-order ticket, input
+ * slots, one 64-byte tile state per tile) lives in a static device array of
+ * about 272 KB that each GPU holds until the process ends; queries of more than
+ * 4096 tiles (n_bits > 2^27) are EINVAL.  Every call on one GPU shares that
+ * array: calls that overlap (on different streams) race, calls on one stream
+ * are ordered.  The input slots go to the device by a pageable copy from a
+ * static host buffer, staged before the call returns.  Always one workgroup per
+ * tile chained by look-back (never the batch of one); the default variant as for
+ * ewah_threshold.  Inputs, outputs, bound, errors as for ewah_threshold.
+ */
+ewah_status ewah_threshold_noalloc(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
+                                   uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream);
+
 /* As ewah_threshold with an explicit kernel variant (ewah_variant_code); the result is identical.
  * variant = 0 takes the default: the unary counter at T <= 2, else ewah_default_variant(). */
 ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,

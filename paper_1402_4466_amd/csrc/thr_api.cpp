@@ -86,9 +86,29 @@ struct Lib {
     size_t d_table_cap = 0;
     uint32_t* d_err = nullptr;
     std::map<hipStream_t, Ctx> ctx;
+    unsigned char* na_ptr = nullptr;   // device address of `scratch` (allocation-free entry point)
+    uint32_t na_epoch = 0;             // launch tag of its tile states
 };
 
 Lib g;
+
+// ------------------------------------------- scratch of the allocation-free query
+// ewah_threshold_noalloc keeps its per-call device state in this file-scope array
+// instead of allocating: the tile-order ticket, the input slots and one tile state
+// per tile.  The host never uses the array's name as an address: ewah_init takes its
+// device address with hipGetSymbolAddress (g.na_ptr) and every kernel argument and
+// copy uses that.  Every call on the GPU shares it, so calls that overlap race.
+constexpr uint32_t NA_MAX_TILES = 4096;   // 2^27 rows per query
+constexpr size_t NA_SLOTS_OFF = 256;      // bytes; the ticket is the first word
+constexpr size_t NA_STATE_OFF = NA_SLOTS_OFF + (((size_t)(MAXN + 1) * 4 + 255) & ~(size_t)255);
+constexpr size_t NA_BYTES = NA_STATE_OFF + (size_t)NA_MAX_TILES * sizeof(TileState);
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+static uint32_t na_host_slots[MAXN + 1];   // host staging of the input slots (static: no allocation)
+
+// Clears n 64-bit words (used instead of hipMemsetAsync so that the call stays capturable).
+__global__ void na_clear_kernel(uint64_t* p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
 
 ewah_status ensure_ready() {
     if (!g.ready) return fail(EWAH_EINVAL, "ewah_init() has not been called");
@@ -348,6 +368,12 @@ ewah_status ewah_init(int device) {
     HIPCHK(set_smem_limits(need));
     HIPCHK(hipMalloc(&g.d_err, 256));
     HIPCHK(hipMemset(g.d_err, 0, 256));
+    // device address of the allocation-free entry point's scratch on this device
+    void* na = nullptr;
+    HIPCHK(hipGetSymbolAddress(&na, HIP_SYMBOL(scratch)));
+    if (!na) return fail(EWAH_EDEVICE, "no device address for the scratch array");
+    g.na_ptr = (unsigned char*)na;
+    g.na_epoch = 0;
     g.ready = true;
     return EWAH_OK;
 }
@@ -702,6 +728,68 @@ ewah_status ewah_threshold_v(const ewah_bitmap* const* in, uint32_t n, uint32_t 
 ewah_status ewah_threshold(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
                            uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream) {
     return run_plain(in, n, T, nullptr, out_words_dev, out_cap, out_n_words_dev, 0, hip_stream);
+}
+
+ewah_status ewah_threshold_noalloc(const ewah_bitmap* const* in, uint32_t n, uint32_t T, uint64_t* out_words_dev,
+                                   uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream) {
+    ewah_status st = ensure_ready();
+    if (st) return st;
+    if (!in || !out_n_words_dev) return fail(EWAH_EINVAL, "null argument");
+    if (n == 0) return fail(EWAH_EINVAL, "n = 0: the number of rows is undefined without an input");
+    if (n > MAXN) return fail(EWAH_EINVAL, "at most " + std::to_string(MAXN) + " inputs per query");
+    uint64_t n_bits = 0, sum_words = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!in[i]) return fail(EWAH_EINVAL, "null bitmap at index " + std::to_string(i));
+        if (i == 0) n_bits = in[i]->stats.n_bits;
+        else if (in[i]->stats.n_bits != n_bits) return fail(EWAH_EINVAL, "inputs have different n_bits");
+        sum_words += in[i]->stats.n_words;
+    }
+    const uint64_t bound = ewah_output_bound(n_bits, sum_words);
+    if (out_cap < bound)
+        return fail(EWAH_ENOSPC, "out_cap " + std::to_string(out_cap) + " < bound " + std::to_string(bound));
+    if (bound && !out_words_dev) return fail(EWAH_EINVAL, "null output");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const uint64_t U = (n_bits + 63) / 64;
+    if (U == 0) {
+        HIPCHK(launch_zero_len(out_n_words_dev, s));
+        return EWAH_OK;
+    }
+    const uint64_t tiles = (U + TW - 1) / TW;
+    if (tiles > NA_MAX_TILES)
+        return fail(EWAH_EINVAL, "ewah_threshold_noalloc: " + std::to_string(tiles) + " tiles of " + std::to_string(TW) +
+                                     " words; its static scratch holds at most " + std::to_string(NA_MAX_TILES) +
+                                     " (n_bits <= " + std::to_string((uint64_t)NA_MAX_TILES * TW * 64) + ")");
+    uint32_t* d_ticket = (uint32_t*)g.na_ptr;
+    uint32_t* d_slots = (uint32_t*)(g.na_ptr + NA_SLOTS_OFF);
+    TileState* d_state = (TileState*)(g.na_ptr + NA_STATE_OFF);
+    // tile states carry a 16-bit launch tag; on a wrap the stale states are cleared
+    if ((++g.na_epoch & 0xFFFFu) == 0) {
+        hipLaunchKernelGGL(na_clear_kernel, dim3(256), dim3(256), 0, s, (uint64_t*)d_state,
+                           (size_t)NA_MAX_TILES * sizeof(TileState) / 8);
+        HIPCHK(hipGetLastError());
+        g.na_epoch = 1;
+    }
+    // input slots: a pageable copy, staged by the runtime before the call returns, so the
+    // static host buffer is free for the next call
+    for (uint32_t i = 0; i < n; ++i) na_host_slots[i] = in[i]->slot;
+    HIPCHK(hipMemcpyAsync(d_slots, na_host_slots, (size_t)n * 4, hipMemcpyHostToDevice, s));
+    QueryDev q{};
+    q.ids = d_slots;
+    q.out = out_words_dev;
+    q.out_n = out_n_words_dev;
+    q.state = d_state;
+    q.stage = nullptr;
+    q.cap = out_cap;
+    q.N = n;
+    q.T = T;
+    q.U = (uint32_t)U;
+    q.tiles = (uint32_t)tiles;
+    q.tail_bits = (uint32_t)(n_bits % 64);
+    q.variant = (T >= 1u && T <= 2u) ? var_make(false, 8, 8, true) : ewah_default_variant();
+    q.pd = nullptr;
+    q.bms = nullptr;
+    HIPCHK(launch_query(q, g.d_table, d_ticket, g.na_epoch, g.d_err, s, PRED_THRESHOLD));
+    return EWAH_OK;
 }
 
 ewah_status ewah_opt_threshold(const ewah_bitmap* const* in, uint32_t n, uint64_t K, uint64_t* out_words_dev,

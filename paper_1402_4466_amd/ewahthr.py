@@ -67,6 +67,7 @@ _get_stats = _sig("ewah_get_stats", _i32, [_vp, ctypes.POINTER(Stats)])
 _device_words = _sig("ewah_device_words", _vp, [_vp])
 _output_bound = _sig("ewah_output_bound", _u64, [_u64, _u64])
 _threshold_v = _sig("ewah_threshold_v", _i32, [ctypes.POINTER(_vp), _u32, _u32, _vp, _u64, _vp, _u32, _vp])
+_threshold_noalloc = _sig("ewah_threshold_noalloc", _i32, [ctypes.POINTER(_vp), _u32, _u32, _vp, _u64, _vp, _vp])
 _symmetric = _sig("ewah_symmetric", _i32, [ctypes.POINTER(_vp), _u32, _vp, _u32, _vp, _u64, _vp, _vp])
 _count_histogram = _sig("ewah_count_histogram", _i32, [ctypes.POINTER(_vp), _u32, _vp, _vp])
 _opt_threshold = _sig("ewah_opt_threshold", _i32, [ctypes.POINTER(_vp), _u32, _u64, _vp, _u64, _vp,
@@ -97,7 +98,7 @@ _mlp_train_step = _sig("ewah_mlp_train_step", _i32, [_vp, _vp, _vp, _u32, ctypes
 _mlp_last_error = _sig("ewah_mlp_last_error", ctypes.c_char_p, [])
 
 EXPORTED = ["ewah_init", "ewah_last_error", "ewah_register", "ewah_register_many", "ewah_release",
-            "ewah_get_stats", "ewah_device_words", "ewah_output_bound", "ewah_threshold", "ewah_threshold_v",
+            "ewah_get_stats", "ewah_device_words", "ewah_output_bound", "ewah_threshold", "ewah_threshold_v", "ewah_threshold_noalloc",
             "ewah_symmetric", "ewah_opt_threshold", "ewah_count_histogram",
             "ewah_variant_code", "ewah_variant_code_ex", "ewah_default_variant", "ewah_batch_plan", "ewah_batch_run",
             "ewah_batch_set_variants", "ewah_batch_set_grid", "ewah_batch_free", "ewah_device_errors",
@@ -235,6 +236,13 @@ def threshold(bitmaps, T: int, out_words_ptr: int, out_cap: int, out_n_ptr: int,
     """Enqueue one T-of-N query; outputs are device pointers (e.g. tensor.data_ptr())."""
     arr, n = _handles(bitmaps)
     _check(_threshold_v(arr, n, T, out_words_ptr, out_cap, out_n_ptr, variant, _stream_ptr(stream)), "threshold")
+
+
+def threshold_noalloc(bitmaps, T: int, out_words_ptr: int, out_cap: int, out_n_ptr: int, stream=None):
+    """As threshold, through the entry point that allocates nothing (its scratch is a static
+    device array shared by every call on the GPU: calls that overlap race)."""
+    arr, n = _handles(bitmaps)
+    _check(_threshold_noalloc(arr, n, T, out_words_ptr, out_cap, out_n_ptr, _stream_ptr(stream)), "threshold_noalloc")
 
 
 def symmetric(bitmaps, f, out_words_ptr: int, out_cap: int, out_n_ptr: int, stream=None):
