@@ -149,9 +149,22 @@ def load_traffic(path, kernel):
     return t["bytes_per_launch"]
 
 
+def stored_digests():
+    """Lengths and digests of the oracle's result for every query of the batched workloads,
+    written by tests/golden/make_batched_digests.py (oracle and generators only)."""
+    path = os.path.join(ROOT, "tests", "golden", "batched_digests.json")
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except OSError:
+        return None
+
+
 def bench_c4(args, E, torch):
+    from paper_1402_4466_amd import autotune as A
     from paper_1402_4466_amd import datagen as D
     from paper_1402_4466_amd import selector as S
+    from paper_1402_4466_amd.workload import PooledBatch
     t0 = time.perf_counter()
     pool, dens = D.config4_pool(args.pool)
     qs = D.queries(D.SEED_BASE + 4, args.queries, args.pool, 2, min(256, args.pool))
@@ -162,34 +175,27 @@ def bench_c4(args, E, torch):
     bms = E.register_many(pool, n_bits)
     log(f"registered in {time.perf_counter() - t0:.1f} s")
     nw = np.array([len(s) for s in pool], dtype=np.int64)
-    in_words = np.array([int(nw[q.idx].sum()) for q in qs], dtype=np.int64)
-    caps = [E.output_bound(n_bits, int(w)) for w in in_words]
-    offs = np.concatenate([[0], np.cumsum(caps)])
-    out = torch.zeros(int(offs[-1]), dtype=torch.int64, device="cuda")
-    out_n = torch.zeros(len(qs), dtype=torch.int64, device="cuda")
-    base, nbase = out.data_ptr(), out_n.data_ptr()
-    out_ptrs = [base + 8 * int(o) for o in offs[:-1]]
-    n_ptrs = [nbase + 8 * i for i in range(len(qs))]
-
-    from paper_1402_4466_amd import autotune as A
-    sel = S.load_selector(args.selector)
-    batch = E.Batch(bms, [(q.idx, q.T) for q in qs], out_ptrs, caps, n_ptrs, grid=E.num_cus(), use_graph=True)
     stream = torch.cuda.current_stream()
-    sel_kind = sel.apply(batch, bms, qs, n_bits, stream)
-    per_step_select = hasattr(sel, "apply_device")
+    sel = S.load_selector(args.selector)
+    signature = f"c4_q{len(qs)}_pool{len(pool)}"
+    pb = PooledBatch(bms, nw, qs, n_bits, selector=sel, signature=signature, stream=stream)
+    batch = pb.batch
+    sel_kind = pb.sel_kind
+    # selection runs once per plan (a batch's features never change): features -> model ->
+    # argmin on the device, timed on its own
+    sel_ms = None
+    if hasattr(sel, "mode"):
+        sel_ms = events_time(lambda: sel.apply(batch, stream), stream, 5)
 
     def step():
-        if per_step_select:
-            sel.apply_device(stream)     # features -> MLP -> argmin on the device
         batch.run(stream)                # one persistent, graph-captured launch of every query
 
-    signature = f"c4_q{len(qs)}_pool{len(pool)}_{sel_kind}"
-    tuned = None if args.retune else A.lookup(signature)
+    tuned = None if args.retune else A.lookup(f"{signature}_{sel_kind}")
     if tuned is None and (args.tune or args.retune):
-        tuned = A.tune_batch(batch, step, signature, E.num_cus(), log=log)
-    grid = int(tuned["grid"]) if tuned else E.num_cus()
+        tuned = A.tune_batch(batch, step, f"{signature}_{sel_kind}", E.num_cus(), log=log)
+    grid = int(tuned["grid"]) if tuned else pb.grid
     batch.set_grid(grid)
-    total_in = int(in_words.sum()) * 8
+    total_in = pb.input_bytes
 
     for _ in range(args.warmup):
         step()
@@ -199,34 +205,58 @@ def bench_c4(args, E, torch):
     ms = events_time(step, stream, args.steps)
     wall = (time.perf_counter() - t_wall) / args.steps * 1e3
     assert E.device_errors() == 0
-    out_words = int(out_n.sum().item())
     value = total_in / (ms / 1e3) / 1e9
+    # every output against the stored oracle digests (outside the timed region)
+    dg = stored_digests()
+    bit_exact, checked = None, 0
+    ns, dig = pb.digests()
+    out_words = int(ns.sum())
+    if dg is not None and dg.get("n_bits") == n_bits and dg.get("pool") == len(pool) and \
+            dg["c4"]["queries"] == len(qs):
+        bad = sum(1 for i in range(len(qs)) if int(ns[i]) != dg["c4"]["words"][i] or dig[i] != dg["c4"]["sha256_16"][i])
+        bit_exact, checked = bad == 0, len(qs)
+        log(f"bit-exact: {len(qs) - bad}/{len(qs)} outputs equal the oracle's (stored digests)")
     log(f"batched ({sel_kind}, grid {grid}): {ms:.3f} ms/step (wall {wall:.3f}), {value:.1f} GB/s input, "
         f"output {out_words} words")
-    # kernel-only time of the persistent launch (same stream, HIP events), for the roofline
-    kms = events_time(lambda: batch.run(stream), stream, args.steps)
     # the same batched launch with every query on the default variant (no selection)
     learned_variants = batch.get_variants()
     batch.set_variants(np.full(len(qs), E.default_variant(), dtype=np.uint32))
     batch.run(stream)
-    dms = events_time(lambda: batch.run(stream), stream, args.steps)
+    dms = events_time(step, stream, args.steps)
     batched_default = total_in / (dms / 1e3) / 1e9
     batch.set_variants(learned_variants)
+    batch.run(stream)
     log(f"batched, default variant: {dms:.3f} ms/step, {batched_default:.1f} GB/s")
+    # kernel-only time of the persistent launch (same stream, HIP events), for the roofline
+    kms = events_time(step, stream, args.steps)
 
-    plain = None
+    plain = plain_dev = None
     if not args.no_plain:
         dv = E.default_variant()
+        ins = [E.Inputs([bms[j] for j in q.idx]) for q in qs]       # marshalled once, as a serving loop would
+        ptrs = [pb.out.data_ptr() + 8 * int(o) for o in pb.offs[:-1]]
+        nptrs = [pb.out_n.data_ptr() + 8 * i for i in range(len(qs))]
 
         def run_plain():
             for i, q in enumerate(qs):
-                E.threshold([bms[j] for j in q.idx], q.T, out_ptrs[i], caps[i], n_ptrs[i], stream=stream,
-                            variant=dv)
+                E.threshold(ins[i], q.T, ptrs[i], pb.caps[i], nptrs[i], stream=stream, variant=dv)
         run_plain()
         torch.cuda.synchronize()
         pms = events_time(run_plain, stream, max(1, min(3, args.steps)))
         plain = total_in / (pms / 1e3) / 1e9
-        log(f"plain: {pms:.3f} ms/step, {plain:.1f} GB/s")
+        # device time of the plain path: per query, events around its enqueued work (upload of
+        # the input slots and its kernels), summed; host gaps between queries excluded
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in qs]
+        for i, q in enumerate(qs):
+            evs[i][0].record(stream)
+            E.threshold(ins[i], q.T, ptrs[i], pb.caps[i], nptrs[i], stream=stream, variant=dv)
+            evs[i][1].record(stream)
+        torch.cuda.synchronize()
+        pdev = sum(a.elapsed_time(b) for a, b in evs)
+        plain_dev = total_in / (pdev / 1e3) / 1e9
+        log(f"plain: {pms:.3f} ms/step, {plain:.1f} GB/s (device time {pdev:.3f} ms, {plain_dev:.1f} GB/s)")
+        batch.run(stream)   # restore the batched outputs
+        torch.cuda.synchronize()
 
     alg_bytes = total_in + 8 * out_words
     achieved = alg_bytes / (kms / 1e3) / 1e9
@@ -234,7 +264,12 @@ def bench_c4(args, E, torch):
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "thr_batch_kernel", "alg_bytes_per_launch": alg_bytes, "kernel_ms": round(kms, 4),
+            "achieved_is": "effective: algorithmic bytes (all input words + output words) per launch time; "
+                           "tiles settled by count bounds read none of their literal words",
             "measured_stream_ceiling_GBps": STREAM_CEILING_GBS}
+    if traffic:
+        roof["traffic_GBps"] = round(traffic / (kms / 1e3) / 1e9, 2)
+        roof["traffic_frac"] = round(traffic / (kms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     cpu = cpu_mt = None
     if not args.no_cpu:
         cpu = cpu_baseline(lambda q: [pool[i] for i in q.idx], n_bits, qs, args.cpu_seconds)
@@ -250,15 +285,21 @@ def bench_c4(args, E, torch):
                                "d log-uniform [1e-4,0.3], N~U[2,256], T~U[1,N]",
                    "path": "batched persistent graph launch", "selector": sel_kind, "grid": grid,
                    "input_bytes_per_step": total_in, "output_words_per_step": out_words},
+        "bit_exact": bit_exact, "bit_exact_outputs_checked": checked,
+        "selection_ms_per_plan": None if sel_ms is None else round(sel_ms, 4),
         "plain_value": None if plain is None else round(plain, 2),
+        "plain_device_value": None if plain_dev is None else round(plain_dev, 2),
         "batched_default_variant_value": round(batched_default, 2),
         "speedup_vs_plain": None if plain is None else round(value / plain, 3),
+        "speedup_vs_plain_device": None if plain_dev is None else round(value / plain_dev, 3),
         "words_per_s": round(total_in / 8 / (ms / 1e3), 1),
         "roofline": roof,
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_mt,
     }
-    batch.free()
+    pb.free()
+    if hasattr(sel, "free"):
+        sel.free()
     return res
 
 
@@ -459,7 +500,7 @@ def bench_index(args, E, torch):
             b = E.Batch(pools[sh], [(q.idx, q.T) for q in qd], [ptrs[i] for i, _, _ in keep],
                         [caps[i] for i, _, _ in keep], [nptrs[i] for i, _, _ in keep], grid=2 * E.num_cus(),
                         use_graph=True)
-            sel_kind = sel.apply(b, pools[sh], qd, ix.n_bits, stream)
+            sel_kind = sel.apply(b, stream)
             signature = f"index_{kind}_{sh}_q{len(qd)}_{sel_kind}"
             tuned = None if args.retune else A.lookup(signature)
             if tuned is None and (args.tune or args.retune):
@@ -526,6 +567,8 @@ def bench_index(args, E, torch):
         log(f"cpu oracle: {cpu}")
     for b in batches:
         b.free()
+    if hasattr(sel, "free"):
+        sel.free()
     n_run = sum(g["queries"] for g in groups)
     return {"metric": "compressed input GB/s for Many-Criteria and Similarity threshold queries (batched)",
             "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -141,10 +141,12 @@ ewah_status ewah_threshold(const ewah_bitmap* const* in, uint32_t n, uint32_t T,
  * Section 5.1: a counter-based method takes any function from [0, N] to the
  * Booleans).  Output row i is f[c_i], where c_i is the number of inputs with
  * row i set and f[0..n] is a host table (f_len = n + 1 bytes, 0 or non-zero),
- * read during the call only.  Supported: any f whose counts giving 1 form at
- * most 8 runs (at least T, at most T, exactly T, ranges, their complements...),
- * and odd or even parity; any other table is EINVAL.  Inputs, output buffers,
- * bound, errors and asynchrony as for ewah_threshold.
+ * read during the call only.  Any table is accepted: tables whose counts giving
+ * 1 form at most 8 runs (at least T, at most T, exactly T, ranges, their
+ * complements...) compare the bit-sliced counts with the runs' ends, odd and even
+ * parity read the lowest count plane, and any other table is looked up per row
+ * (one bit per count, staged in LDS).  Inputs, output buffers, bound, errors and
+ * asynchrony as for ewah_threshold.
  */
 ewah_status ewah_symmetric(const ewah_bitmap* const* in, uint32_t n, const uint8_t* f, uint32_t f_len,
                            uint64_t* out_words_dev, uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream);
@@ -213,6 +215,15 @@ uint32_t ewah_variant_code(int dense, uint32_t walk, uint32_t litwalk);
  * counter runs; dense is then ignored.  The result never depends on the code.
  */
 uint32_t ewah_variant_code_ex(int dense, uint32_t walk, uint32_t litwalk, int looped);
+/*
+ * As ewah_variant_code_ex, plus the gate of the per-group count bounds (RBMrg's
+ * second case, Section 6.4, applied to groups of words inside a tile that its run
+ * counts do not settle): gate 0 counts them when T exceeds 1.1 times the mean
+ * bound (the default), 1 always, 2 never, 3 when T exceeds 1.5 times the mean
+ * bound.  Bounds only drop words that cannot reach T: the result never depends on
+ * the code.
+ */
+uint32_t ewah_variant_code_full(int dense, uint32_t walk, uint32_t litwalk, int looped, uint32_t gate);
 uint32_t ewah_default_variant(void);
 
 /* ------------------------------------------------------------ batched path */
@@ -297,6 +308,86 @@ ewah_status ewah_batch_select(ewah_batch* b, const float* pred_dev, uint32_t n_a
 
 /* Copies the variant codes currently stored in the batch's device query records to host (synchronous). */
 ewah_status ewah_batch_get_variants(ewah_batch* b, uint32_t* variants_host);
+
+/*
+ * Cost of every query inside the batch, the labels of the learned selector
+ * (trained on timings the method itself generates; the paper takes the minimum
+ * of repeated runs as the true time, Section 7.5): runs the batch reps times
+ * (eager launches, the batch's grid and variants) and writes, per query, the
+ * minimum over the runs of the time the workgroups spent on its tiles, in
+ * microseconds (device wall clock), into busy_us[nq] (host).  A persistent
+ * launch takes about the sum of these times divided by its grid.  Synchronous.
+ */
+ewah_status ewah_batch_time_queries(ewah_batch* b, uint32_t reps, float* busy_us, void* hip_stream);
+
+/* --------------------------------------------------------------- selector */
+
+/*
+ * The variant selector as a library object: a learned cost model (an FP32 MLP
+ * predicting every variant's log-time from the 16 query features; machine-
+ * learned algorithm selection is the paper's future work, Section 9) and the
+ * paper-style rule set (per variant a running-time model of the forms of
+ * Section 8.1 -- compressed size, size times ln N, N times tiles, T times size,
+ * dirty words -- fitted by least squares; hybrid H takes the smallest estimate,
+ * Section 8.2).  The variant with the smallest prediction is taken; selection
+ * never changes a result.
+ */
+typedef struct ewah_selector ewah_selector;
+enum { EWAH_SELECT_MLP = 0, EWAH_SELECT_RULES = 1 };
+
+/* Training settings; zero fields take the defaults (80 epochs, batch 1024, lr 2e-3, seed 1). */
+typedef struct {
+    uint32_t epochs;
+    uint32_t batch;
+    float lr;
+    uint64_t seed;
+} ewah_train_config;
+
+/*
+ * Loads a model file (JSON object: "arm_codes" [K], "mu" [16], "sigma" [16],
+ * "params_raw" [P], optionally "params_folded" [P] and "rules_coef" [5][K]; P =
+ * ewah_mlp_num_params(K); other keys are ignored) and uploads the network.
+ * EFORMAT if a key is missing or malformed.  *out is owned by the caller until
+ * ewah_selector_free().  Host only: the device copy of the network is made by the
+ * first prediction (ewah_init must have been called by then).
+ */
+ewah_status ewah_selector_load(const char* path, ewah_selector** out);
+/* Writes the model in the format ewah_selector_load reads. */
+ewah_status ewah_selector_save(const ewah_selector* s, const char* path);
+void ewah_selector_free(ewah_selector* s);
+uint32_t ewah_selector_num_arms(const ewah_selector* s);
+/* Variant codes of the arms (K entries, host). */
+ewah_status ewah_selector_arm_codes(const ewah_selector* s, uint32_t* codes);
+
+/*
+ * Trains a selector on n labelled queries: feat [n][16] (host; the features of
+ * ewah_query_features), log2_time [n][n_arms] (host; log2 of each arm's measured
+ * time in microseconds, e.g. from ewah_batch_time_queries), arm_codes [n_arms].
+ * The features are standardised over the set (the constant feature stays 1);
+ * the targets are each arm's log-time minus the query's mean over the arms.
+ * The network is trained on the GPU by the library's forward, backward and
+ * Adam kernels (mean squared error, mini-batches shuffled by a counter-based
+ * SplitMix64 stream of cfg->seed); the standardisation is then folded into the
+ * first layer.  The rule set is fitted on the same labels.  Synchronous; *out is
+ * owned by the caller.  EINVAL for empty sets, more than 16 arms or non-finite labels.
+ */
+ewah_status ewah_selector_train(const float* feat, const float* log2_time, uint32_t n, uint32_t n_arms,
+                                const uint32_t* arm_codes, const ewah_train_config* cfg, ewah_selector** out);
+/* Training loss (mean squared error) of the last epoch's last mini-batch. */
+float ewah_selector_train_loss(const ewah_selector* s);
+
+/* pred_dev [n][K] = predicted cost of every arm for feat_dev [n][16] (device memory, asynchronous):
+ * mode EWAH_SELECT_MLP (relative log2-time) or EWAH_SELECT_RULES (microseconds). */
+ewah_status ewah_selector_predict(const ewah_selector* s, int mode, const float* feat_dev, uint32_t n, float* pred_dev,
+                                  void* hip_stream);
+
+/*
+ * Features, prediction and per-query argmin for a planned batch, all on the device
+ * (no host round trip): the chosen variant codes land in the batch's query records and
+ * the next ewah_batch_run uses them.  The features of a batch do not change, so one
+ * call per plan is enough.  Asynchronous on hip_stream.
+ */
+ewah_status ewah_batch_select_model(ewah_batch* b, const ewah_selector* s, int mode, void* hip_stream);
 
 /*
  * FP32 multilayer perceptron 16 -> 64 -> 64 -> n_out (ReLU), the cost model

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libewahthr.so")
 GENLIB = os.path.join(HERE, "datagen", "libewahgen.so")
 
-HIP_SOURCES = ["thr_tile.hip", "thr_api.cpp", "select.hip", "mlp.hip"]
+HIP_SOURCES = ["thr_tile.hip", "thr_api.cpp", "select.hip", "mlp.hip", "selector.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HIP_FLAGS = [

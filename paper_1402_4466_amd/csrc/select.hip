@@ -87,6 +87,33 @@ __global__ void select_kernel(const float* __restrict__ pred, uint32_t nq, uint3
     qs[q].variant = codes[best];
 }
 
+// Rule set (Section 8.1 model forms): predicted time of arm k = sum_j x_j coef[j][k], with
+// x the five regressors of the paper-style running-time model computed from the features:
+// EWAHSize (compressed words), EWAHSize ln N, N times tiles, T EWAHSize, dirty words.
+__global__ void rules_kernel(const float* __restrict__ feat, uint32_t nq, const float* __restrict__ coef, uint32_t K,
+                             float* __restrict__ pred) {
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const float* f = feat + (size_t)q * 16;
+    const float ewah = exp2f(f[10]) - 1.f;
+    const float N = exp2f(f[0]);
+    const float T = exp2f(f[1]);
+    const float tiles = fmaxf(exp2f(f[13]) / 65536.f, 1.f);
+    const float x[5] = {ewah, ewah * logf(fmaxf(N, 1.f)), N * tiles, T * ewah, f[12] * ewah};
+    for (uint32_t k = 0; k < K; ++k) {
+        float s = 0.f;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) s = fmaf(x[j], coef[(size_t)j * K + k], s);
+        pred[(size_t)q * K + k] = s;
+    }
+}
+
+hipError_t launch_rules(const float* feat, uint32_t nq, const float* coef, uint32_t K, float* pred, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    hipLaunchKernelGGL(rules_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, feat, nq, coef, K, pred);
+    return hipGetLastError();
+}
+
 hipError_t launch_features(const QueryDev* qs, uint32_t nq, const float4* stats, float r, float* feat, hipStream_t s) {
     if (nq == 0) return hipSuccess;
     hipLaunchKernelGGL(features_kernel, dim3((nq + 3) / 4), dim3(256), 0, s, qs, nq, stats, r, feat);

@@ -42,6 +42,10 @@ struct Arena {
 
 }  // namespace
 
+namespace ewt {
+void set_last_error(const std::string& msg) { g_err = msg; }
+}
+
 struct ewah_bitmap {
     BitmapDev dev;        // device pointers into the arena
     uint32_t slot = 0;    // index in the device table
@@ -390,6 +394,9 @@ uint32_t ewah_variant_code(int dense, uint32_t walk, uint32_t litwalk) { return 
 uint32_t ewah_variant_code_ex(int dense, uint32_t walk, uint32_t litwalk, int looped) {
     return var_make(dense != 0, walk, litwalk, looped != 0);
 }
+uint32_t ewah_variant_code_full(int dense, uint32_t walk, uint32_t litwalk, int looped, uint32_t gate) {
+    return var_make(dense != 0, walk, litwalk, looped != 0, gate);
+}
 uint32_t ewah_default_variant(void) { return var_make(true, 8, 8); }
 
 ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device, ewah_bitmap** out) {
@@ -538,7 +545,7 @@ namespace {
 // uploaded with the input slots) when it is not null.
 ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, const PredDev* pred,
                       uint64_t* out_words_dev, uint64_t out_cap, uint64_t* out_n_words_dev, uint32_t variant,
-                      void* hip_stream) {
+                      void* hip_stream, const uint32_t* tab = nullptr) {
     ewah_status st = ensure_ready();
     if (st) return st;
     // the largest-count and histogram passes write no output
@@ -567,6 +574,11 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
     // staging: the n slots, then (8-byte aligned) the predicate record
     const size_t pred_off = ((size_t)n + 1) & ~(size_t)1;
     size_t n_stage = pred ? pred_off + sizeof(PredDev) / 4 : n;
+    // a general table (PRED_TABLE) follows the predicate record: bit c = f(c), c = 0..n
+    const size_t tab_off = n_stage;
+    const size_t tab_words = (pred && pred->kind == PRED_TABLE) ? ((size_t)n + 32) / 32 : 0;
+    if (tab_words && !tab) return fail(EWAH_EINVAL, "null function table");
+    n_stage += tab_words;
     // A threshold query with more tiles than resident workgroups runs as a
     // batch of one on the persistent kernel: its tiles are taken in turn from per-XCD
     // ranges and placed by a scan, instead of one workgroup per tile chained by
@@ -611,7 +623,14 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
     q.pd = pred ? (const PredDev*)(c->d_ids + pred_off) : nullptr;
     HIPCHK(hipEventSynchronize(c->ev));   // previous upload from the staging buffer is done
     for (uint32_t i = 0; i < n; ++i) c->h_ids[i] = in[i]->slot;
-    if (pred) std::memcpy(c->h_ids + pred_off, pred, sizeof(PredDev));
+    if (pred) {
+        PredDev pc = *pred;
+        if (tab_words) {
+            pc.tab = (const uint32_t*)(c->d_ids + tab_off);
+            std::memcpy(c->h_ids + tab_off, tab, tab_words * 4);
+        }
+        std::memcpy(c->h_ids + pred_off, &pc, sizeof(PredDev));
+    }
     if (batched) {
         std::memcpy(c->h_ids + q_off, &q, sizeof(QueryDev));
         c->h_ids[qt_off] = 0u;
@@ -679,8 +698,8 @@ ewah_status count_histogram(const ewah_bitmap* const* in, uint32_t n, uint64_t* 
 }
 
 // Device form of a symmetric function given by its table f[0..n]: the runs of counts
-// giving 1 as intervals (at most MAX_IV), or parity; EINVAL otherwise.
-ewah_status pred_from_table(const uint8_t* f, uint32_t n, PredDev& pd) {
+// giving 1 as intervals (at most MAX_IV), parity, or else the table itself as bits (tab).
+ewah_status pred_from_table(const uint8_t* f, uint32_t n, PredDev& pd, std::vector<uint32_t>& tab) {
     pd = PredDev{};
     uint32_t k = 0;
     bool fits = true;
@@ -707,12 +726,19 @@ ewah_status pred_from_table(const uint8_t* f, uint32_t n, PredDev& pd) {
         odd = odd && ((f[c] != 0) == ((c & 1u) != 0));
         even = even && ((f[c] != 0) == ((c & 1u) == 0));
     }
-    if (!odd && !even) return fail(EWAH_EINVAL, "symmetric function with more than " + std::to_string(MAX_IV) +
-                                                    " runs of counts giving 1 that is not parity");
-    pd = PredDev{};
-    pd.kind = odd ? PRED_ODD : PRED_EVEN;
-    pd.tz = 1;
-    pd.v0 = even ? 1u : 0u;
+    if (odd || even) {
+        pd = PredDev{};
+        pd.kind = odd ? PRED_ODD : PRED_EVEN;
+        pd.tz = 1;
+        pd.v0 = even ? 1u : 0u;
+        return EWAH_OK;
+    }
+    // any other table: looked up per row (bit c of the table is f(c))
+    pd.kind = PRED_TABLE;
+    pd.n_iv = 0;
+    tab.assign(((size_t)n + 32) / 32, 0u);
+    for (uint32_t c = 0; c <= n; ++c)
+        if (f[c]) tab[c >> 5] |= 1u << (c & 31u);
     return EWAH_OK;
 }
 
@@ -837,10 +863,13 @@ ewah_status ewah_symmetric(const ewah_bitmap* const* in, uint32_t n, const uint8
                            uint64_t* out_words_dev, uint64_t out_cap, uint64_t* out_n_words_dev, void* hip_stream) {
     if (!f) return fail(EWAH_EINVAL, "null function table");
     if (f_len != n + 1) return fail(EWAH_EINVAL, "the function table needs n + 1 entries (counts 0..n)");
+    if (n > MAXN) return fail(EWAH_EINVAL, "at most " + std::to_string(MAXN) + " inputs per query");
     PredDev pd;
-    ewah_status st = pred_from_table(f, n, pd);
+    std::vector<uint32_t> tab;
+    ewah_status st = pred_from_table(f, n, pd, tab);
     if (st) return st;
-    return run_plain(in, n, pd.tz, &pd, out_words_dev, out_cap, out_n_words_dev, 0, hip_stream);
+    return run_plain(in, n, pd.tz, &pd, out_words_dev, out_cap, out_n_words_dev, 0, hip_stream,
+                     tab.empty() ? nullptr : tab.data());
 }
 
 ewah_status ewah_device_errors(uint32_t* flags) {
@@ -870,6 +899,9 @@ struct ewah_batch {
     uint32_t total = 0;            // (query, tile) items
     uint32_t* d_work = nullptr;    // WORK_WORDS words: epoch at [1], per-XCD item counters
     uint32_t* d_codes = nullptr;   // variant codes for ewah_batch_select
+    float* d_feat = nullptr;       // features [nq][16] and predictions [nq][16] of ewah_batch_select_model
+    float* d_pred = nullptr;
+    uint32_t* d_itemt = nullptr;   // per-item busy ticks of ewah_batch_time_queries
     std::vector<uint32_t> h_codes; // their host copy (upload only on change)
     uint64_t n_bits = 0;
     uint32_t nq = 0;
@@ -1043,6 +1075,9 @@ void ewah_batch_free(ewah_batch* b) {
     (void)hipFree(b->d_tq);
     (void)hipFree(b->d_work);
     (void)hipFree(b->d_codes);
+    if (b->d_feat) (void)hipFree(b->d_feat);
+    if (b->d_pred) (void)hipFree(b->d_pred);
+    if (b->d_itemt) (void)hipFree(b->d_itemt);
     delete b;
 }
 
@@ -1104,6 +1139,51 @@ ewah_status ewah_batch_select(ewah_batch* b, const float* pred_dev, uint32_t n_a
         b->h_codes.assign(arm_codes, arm_codes + n_arms);
     }
     HIPCHK(launch_select(pred_dev, b->nq, n_arms, b->d_codes, b->d_qs, s));
+    return EWAH_OK;
+}
+
+ewah_status ewah_batch_select_model(ewah_batch* b, const ewah_selector* sel, int mode, void* hip_stream) {
+    if (!b || !sel) return fail(EWAH_EINVAL, "null argument");
+    const uint32_t K = ewah_selector_num_arms(sel);
+    if (K == 0 || K > 16) return fail(EWAH_EINVAL, "selector has no arms");
+    if (!b->d_feat) {
+        HIPCHK(hipMalloc(&b->d_feat, (size_t)b->nq * 16 * sizeof(float)));
+        HIPCHK(hipMalloc(&b->d_pred, (size_t)b->nq * 16 * sizeof(float)));
+    }
+    uint32_t codes[16];
+    ewah_status st = ewah_selector_arm_codes(sel, codes);
+    if (st) return st;
+    st = ewah_batch_features(b, b->d_feat, hip_stream);
+    if (st) return st;
+    st = ewah_selector_predict(sel, mode, b->d_feat, b->nq, b->d_pred, hip_stream);
+    if (st) return st;
+    return ewah_batch_select(b, b->d_pred, K, codes, hip_stream);
+}
+
+ewah_status ewah_batch_time_queries(ewah_batch* b, uint32_t reps, float* busy_us, void* hip_stream) {
+    if (!b || !busy_us || reps == 0) return fail(EWAH_EINVAL, "bad arguments");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (!b->d_itemt) HIPCHK(hipMalloc(&b->d_itemt, std::max<size_t>(b->total, 1) * 4));
+    int khz = 0;
+    HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g.device));
+    if (khz <= 0) return fail(EWAH_EDEVICE, "device reports no wall-clock rate");
+    std::vector<uint32_t> qtile(b->nq + 1);
+    HIPCHK(hipMemcpy(qtile.data(), b->d_qtile, (b->nq + 1) * 4, hipMemcpyDeviceToHost));
+    std::vector<uint32_t> ticks(b->total);
+    std::vector<double> best(b->nq, 1e300);
+    for (uint32_t r = 0; r < reps; ++r) {
+        HIPCHK(launch_bump(b->d_work, s));
+        HIPCHK(launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1, g.d_err,
+                            b->grid, b->smem, s, b->d_itemt));
+        HIPCHK(hipMemcpyAsync(ticks.data(), b->d_itemt, (size_t)b->total * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (uint32_t q = 0; q < b->nq; ++q) {
+            double t = 0;
+            for (uint32_t i = qtile[q]; i < qtile[q + 1]; ++i) t += ticks[i];
+            best[q] = std::min(best[q], t);
+        }
+    }
+    for (uint32_t q = 0; q < b->nq; ++q) busy_us[q] = (float)(best[q] * 1e3 / khz);
     return EWAH_OK;
 }
 

@@ -117,11 +117,12 @@ enum : uint32_t {
     PRED_EVEN = 3,        // count even
     PRED_MAXCOUNT = 4,    // no output: the largest row count goes to *acc (atomic maximum)
     PRED_HIST = 5,        // no output: acc[c] += rows of count c, for c = 1..N (count histogram)
+    PRED_TABLE = 6,       // any f: bit c of tab is f(c), c = 0..N
 };
 constexpr int MAX_IV = 8;
 
 // Predicate of a query other than a plain threshold (device memory).
-struct PredDev {          // 88 bytes
+struct PredDev {          // 96 bytes
     uint32_t kind;        // PRED_*
     uint32_t n_iv;        // PRED_INTERVALS: sorted, disjoint intervals of counts giving 1
     uint32_t tz;          // every count below tz gives v0
@@ -129,7 +130,9 @@ struct PredDev {          // 88 bytes
     uint32_t iv[2 * MAX_IV];
     unsigned long long* acc;   // PRED_MAXCOUNT: running maximum; else, if not null, receives
                                // the number of output rows (added)
+    const uint32_t* tab;  // PRED_TABLE: (N + 32) / 32 words, bit c = f(c)
 };
+constexpr uint32_t TAB_WORDS = (MAXN + 32) / 32;   // words of the largest table (counts 0..MAXN)
 
 struct QueryDev {         // 88 bytes
     const uint32_t* ids;  // N bitmap slots
@@ -152,18 +155,61 @@ enum : uint32_t {
     VAR_WALK_SHIFT = 8,         // bits 8..15: max compressed words for a one-lane walk
     VAR_LITWALK_SHIFT = 16,     // bits 16..23: max literal-block words for a one-lane loop
     VAR_LOOPED = 1u << 24,      // unary (saturating) per-row counter, for T <= planes_for(N)
+    VAR_GATE_SHIFT = 25,        // bits 25..26: when the per-group bounds are counted (GATE_*)
     VAR_EXPLICIT = 1u << 31,    // set in every explicit code so that 0 can mean "default"
 };
+// Gate of the per-group bounds of a tile that is not settled by its run counts:
+// counted when T exceeds 1.1 times the mean bound (default), always, never, or when T
+// exceeds 1.5 times the mean bound.  Bounds only drop groups that cannot reach T, so
+// every gate gives the same result.
+enum : uint32_t { GATE_1_1 = 0, GATE_ALWAYS = 1, GATE_NEVER = 2, GATE_1_5 = 3 };
 
-__host__ __device__ inline uint32_t var_make(bool dense, uint32_t walk, uint32_t litwalk, bool looped = false) {
+__host__ __device__ inline uint32_t var_make(bool dense, uint32_t walk, uint32_t litwalk, bool looped = false,
+                                             uint32_t gate = GATE_1_1) {
     return VAR_EXPLICIT | (dense ? VAR_DENSE : 0u) | ((walk & 255u) << VAR_WALK_SHIFT) |
-           ((litwalk & 255u) << VAR_LITWALK_SHIFT) | (looped ? VAR_LOOPED : 0u);
+           ((litwalk & 255u) << VAR_LITWALK_SHIFT) | (looped ? VAR_LOOPED : 0u) | ((gate & 3u) << VAR_GATE_SHIFT);
 }
 
 __host__ __device__ inline int planes_for(uint32_t n) {
     int p = 1;
     while (p < MAXP && (n >> p) != 0) ++p;
     return p;
+}
+
+// Bit-sliced counts: word p * stride of `planes` holds bit p of the counts of the 64
+// rows of a word (least significant plane first), as in the bit-sliced index of
+// Section 5.3.1.  The rows whose count is at least x (the final comparison of BSTM,
+// there against T - 1): from the top plane down, a row is greater once it has a 1
+// where x has a 0 while all higher bits were equal, and equal while every bit matches.
+__host__ __device__ __forceinline__ uint64_t sliced_ge(const uint64_t* planes, int stride, int P, int x) {
+    if (x <= 0) return ~0ull;
+    if (x >= (1 << P)) return 0ull;
+    uint64_t gt = 0, eq = ~0ull;
+    for (int p = P - 1; p >= 0; --p) {
+        const uint64_t a = planes[p * stride];
+        const uint64_t tb = ((x >> p) & 1) ? ~0ull : 0ull;
+        gt |= eq & a & ~tb;
+        eq &= ~(a ^ tb);
+    }
+    return gt | eq;
+}
+
+// Largest count among the rows of cand (0 if cand is empty): from the top plane down,
+// keep the candidates holding a 1 whenever any does.
+__host__ __device__ __forceinline__ uint32_t sliced_max(const uint64_t* planes, int stride, int P, uint64_t cand) {
+    uint32_t m = 0;
+    for (int p = P - 1; p >= 0; --p) {
+        const uint64_t tb = cand & planes[p * stride];
+        if (tb) { cand = tb; m |= 1u << p; }
+    }
+    return m;
+}
+
+// Count of row r (0..63) read back from the planes.
+__host__ __device__ __forceinline__ uint32_t sliced_row(const uint64_t* planes, int stride, int P, uint32_t r) {
+    uint32_t c = 0;
+    for (int p = 0; p < P; ++p) c |= (uint32_t)((planes[p * stride] >> r) & 1ull) << p;
+    return c;
 }
 
 // The unary counter keeps one level per count 1..T in the planes' storage, so it
@@ -198,7 +244,7 @@ hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* tic
                         hipStream_t s, uint32_t pred_kind = PRED_THRESHOLD);   // kind of *q.pd
 hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_t* tq, uint32_t nq, uint32_t total,
                         const BitmapDev* table, uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid,
-                        size_t smem, hipStream_t s);
+                        size_t smem, hipStream_t s, uint32_t* item_t = nullptr);   // item_t: per-item busy time
 hipError_t launch_bump(uint32_t* work, hipStream_t s);   // epoch at work[1], counters cleared
 hipError_t launch_zero_len(uint64_t* out_n, hipStream_t s);
 hipError_t set_smem_limits(size_t max_bytes);

@@ -473,24 +473,24 @@ __device__ __forceinline__ bool pred_uniform(const QueryDev& q, uint32_t lo, uin
         }
         return hi <= end;
     }
+    if (kind == PRED_TABLE) {
+        // constant iff the table's bits lo..hi are all equal to bit lo
+        const EWT_GLOBAL uint32_t* tab = gp(pd->tab);
+        v = (tab[lo >> 5] >> (lo & 31u)) & 1u;
+        const uint32_t want = v ? ~0u : 0u;
+        for (uint32_t w = lo >> 5; w <= (hi >> 5); ++w) {
+            uint32_t m = ~0u;
+            if (w == (lo >> 5)) m &= ~0u << (lo & 31u);
+            if (w == (hi >> 5)) m &= (hi & 31u) == 31u ? ~0u : ((1u << ((hi & 31u) + 1u)) - 1u);
+            if ((tab[w] ^ want) & m) return false;
+        }
+        return true;
+    }
     // parity: constant only where every count is the same
     v = (lo & 1u) ^ (kind == PRED_EVEN ? 1u : 0u);
     return lo == hi;
 }
 
-// Rows with count >= x, where the count of each of the 64 rows of a word is held
-// bit-sliced in R[0..P-1] (least significant plane first).
-__device__ __forceinline__ uint64_t sliced_ge(const uint64_t* R, int P, int x) {
-    if (x <= 0) return ~0ull;
-    if (x >= (1 << P)) return 0ull;
-    uint64_t gt = 0, eq = ~0ull;
-    for (int p = P - 1; p >= 0; --p) {
-        const uint64_t tb = ((x >> p) & 1) ? ~0ull : 0ull;
-        gt |= eq & R[p] & ~tb;
-        eq &= ~(R[p] ^ tb);
-    }
-    return gt | eq;
-}
 
 // Per-group input counts from presence words staged in LDS word-major (word w of
 // input k at w * pcap + k) for the first ns inputs.  QS lanes share a quad of groups
@@ -689,7 +689,10 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     pm.sh = gsh;
     pm.ng = ng;
     pm.on = false;
-    if (mode == 0 && misc[M_DFULL] < Tz && 10ull * Tz * ngv > 11ull * misc[M_PSUM]) {
+    const uint32_t gate = (q.variant >> VAR_GATE_SHIFT) & 3u;
+    const uint64_t gnum = gate == GATE_1_5 ? 15ull : 11ull;
+    if (mode == 0 && misc[M_DFULL] < Tz && gate != GATE_NEVER &&
+        (gate == GATE_ALWAYS || 10ull * Tz * ngv > gnum * misc[M_PSUM])) {
         if (fine) count_quads<4>(prs, PCAP_FINE, min(N, PCAP_FINE), gcnt);
         else count_quads<16>(prs, PCAP_COARSE, min(N, PCAP_COARSE), gcnt);
         if (N > pcap) {   // the rest of very wide queries (4-word groups): wavefront ballots
@@ -931,9 +934,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             while (any) {
                 const int r = __builtin_ctzll(any);
                 any &= any - 1ull;
-                uint32_t c = 0;
-#pragma unroll
-                for (int p = 0; p < MAXP; ++p) c |= (uint32_t)((R[p] >> r) & 1ull) << p;
+                const uint32_t c = sliced_row(R, 1, MAXP, (uint32_t)r);
                 atomicAdd(&hl[c + k1], 1u);
             }
         }
@@ -945,17 +946,23 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         // largest planes value over the word's valid rows (bit-sliced maximum: keep the
         // rows holding the highest plane bit seen so far), plus the position's one-fills
         if ((uint32_t)tid < nPos) {
-            uint64_t cand = (tS + (uint32_t)tid == U - 1u && q.tail_bits) ? ((1ull << q.tail_bits) - 1ull) : ~0ull;
-            uint32_t m = 0;
-            for (int p = P - 1; p >= 0; --p) {
-                const uint64_t tb = cand & planes[p * TW + tid];
-                if (tb) { cand = tb; m |= 1u << p; }
-            }
+            const uint64_t cand = (tS + (uint32_t)tid == U - 1u && q.tail_bits) ? ((1ull << q.tail_bits) - 1ull) : ~0ull;
+            const uint32_t m = sliced_max(planes + tid, TW, P, cand);
             atomicMax(&misc[M_MAX], m + k1);
         }
         __syncthreads();
         if (tid == 0) atomicMax(q.pd->acc, (unsigned long long)misc[M_MAX]);
         return;
+    }
+    // a general table goes to LDS (the window list is free now): bit c of ftab is f(c)
+    const uint32_t* ftab = (const uint32_t*)win;
+    if constexpr (GENERAL) {
+        if (mode == 0 && q.pd->kind == PRED_TABLE) {
+            uint32_t* ft = (uint32_t*)win;
+            const uint32_t nw = (N + 32u) / 32u;
+            for (uint32_t i = (uint32_t)tid; i < nw; i += BLOCK) ft[i] = gp(q.pd->tab)[i];
+        }
+        __syncthreads();
     }
     uint64_t o = 0;
     if ((uint32_t)tid < nPos) {
@@ -966,12 +973,18 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             uint64_t R[MAXP];
 #pragma unroll
             for (int p = 0; p < MAXP; ++p) R[p] = p < P ? planes[p * TW + tid] : 0ull;
-            if (pd->kind == PRED_INTERVALS) {
+            if (pd->kind == PRED_TABLE) {
+                // per row: its count (planes value plus the word's one-fills) indexes the table
+                for (uint32_t r = 0; r < 64u; ++r) {
+                    const uint32_t c = k1 + sliced_row(R, 1, P, r);
+                    o |= (uint64_t)((ftab[c >> 5] >> (c & 31u)) & 1u) << r;
+                }
+            } else if (pd->kind == PRED_INTERVALS) {
                 // count in [a, b]  <=>  planes in [a - k1, b - k1]
                 const uint32_t n_iv = pd->n_iv;
                 for (uint32_t j = 0; j < n_iv; ++j) {
                     const int lo = (int)pd->iv[2 * j] - (int)k1, hi = (int)pd->iv[2 * j + 1] - (int)k1;
-                    o |= sliced_ge(R, P, lo) & ~sliced_ge(R, P, hi + 1);
+                    o |= sliced_ge(R, 1, P, lo) & ~sliced_ge(R, 1, P, hi + 1);
                 }
             } else {   // parity of planes + k1: plane 0 flipped when k1 is odd
                 o = R[0] ^ (((k1 & 1u) ^ (pd->kind == PRED_EVEN ? 1u : 0u)) ? ~0ull : 0ull);
@@ -981,19 +994,8 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             const int tp = (int)T - (int)k1;
             o = tp <= 0 ? ~0ull : planes[(tp - 1) * TW + tid];
         } else {
-            int tp = (int)T - (int)k1;
-            if (tp <= 0) o = ~0ull;
-            else if (tp >= (1 << P)) o = 0;
-            else {
-                uint64_t gt = 0, eq = ~0ull;
-                for (int p = P - 1; p >= 0; --p) {
-                    uint64_t a = planes[p * TW + tid];
-                    uint64_t tb = ((tp >> p) & 1) ? ~0ull : 0ull;
-                    gt |= eq & a & ~tb;
-                    eq &= ~(a ^ tb);
-                }
-                o = gt | eq;
-            }
+            // count >= T  <=>  planes >= T - k1
+            o = sliced_ge(planes + tid, TW, P, (int)T - (int)k1);
         }
         if (tS + (uint32_t)tid == U - 1u && q.tail_bits) o &= (1ull << q.tail_bits) - 1ull;
     }
@@ -1368,10 +1370,13 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_max_kernel(QueryDev q, con
 // are read through one L2.  A workgroup takes the next item of its own range from
 // that range's counter and, once the range is used up, items of the other ranges in
 // turn.  qtile[i] = first item of query i (qtile[nq] = total); tq[i] = query of item i.
+// item_t (null: off): per item, the wall-clock ticks its workgroup spent on it, the
+// measure of each query's cost inside a batch.
 __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
                                                           const uint32_t* __restrict__ tq, uint32_t nq,
                                                           const BitmapDev* __restrict__ table,
-                                                          uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err) {
+                                                          uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err,
+                                                          uint32_t* __restrict__ item_t) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_item, s_q;
     const uint32_t total = qtile[nq];
@@ -1396,9 +1401,11 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __r
         const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_item);
         const uint32_t qi = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_q);
         if (it >= total) break;
+        const uint64_t t0 = item_t ? wall_clock64() : 0ull;
         QueryDev q = qs[qi];
         if (use_looped(q.variant, q.N, q.T)) process_tile<true, false, false, true>(q, table, it - qtile[qi], epoch, smem, err, it);
         else process_tile<true>(q, table, it - qtile[qi], epoch, smem, err, it);
+        if (item_t && threadIdx.x == 0) item_t[it] = (uint32_t)(wall_clock64() - t0);
     }
 }
 
@@ -1473,8 +1480,9 @@ hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* tic
 
 hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_t* tq, uint32_t nq, uint32_t total,
                         const BitmapDev* table, uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid,
-                        size_t smem, hipStream_t s) {
-    hipLaunchKernelGGL(thr_batch_kernel, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work, epoch_ptr, err);
+                        size_t smem, hipStream_t s, uint32_t* item_t) {
+    hipLaunchKernelGGL(thr_batch_kernel, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work, epoch_ptr, err,
+                       item_t);
     hipLaunchKernelGGL(scan_batch_kernel, dim3(nq), dim3(SCAN_THREADS), 0, s, qs, epoch_ptr, err);
     hipLaunchKernelGGL(place_batch_kernel, dim3((total + 3) / 4), dim3(256), 0, s, qs, qtile, tq, total, epoch_ptr, err);
     return hipGetLastError();

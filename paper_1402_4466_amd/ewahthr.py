@@ -87,6 +87,25 @@ _query_features = _sig("ewah_query_features", _i32, [ctypes.POINTER(_vp), _u32, 
 _batch_features = _sig("ewah_batch_features", _i32, [_vp, _vp, _vp])
 _batch_select = _sig("ewah_batch_select", _i32, [_vp, _vp, _u32, _vp, _vp])
 _batch_get_variants = _sig("ewah_batch_get_variants", _i32, [_vp, _vp])
+_batch_time_queries = _sig("ewah_batch_time_queries", _i32, [_vp, _u32, _vp, _vp])
+_batch_select_model = _sig("ewah_batch_select_model", _i32, [_vp, _vp, _i32, _vp])
+_variant_code_full = _sig("ewah_variant_code_full", _u32, [_i32, _u32, _u32, _i32, _u32])
+
+
+class TrainConfig(ctypes.Structure):
+    _fields_ = [("epochs", _u32), ("batch", _u32), ("lr", ctypes.c_float), ("seed", _u64)]
+
+
+_selector_load = _sig("ewah_selector_load", _i32, [ctypes.c_char_p, ctypes.POINTER(_vp)])
+_selector_save = _sig("ewah_selector_save", _i32, [_vp, ctypes.c_char_p])
+_selector_free = _sig("ewah_selector_free", None, [_vp])
+_selector_num_arms = _sig("ewah_selector_num_arms", _u32, [_vp])
+_selector_arm_codes = _sig("ewah_selector_arm_codes", _i32, [_vp, _vp])
+_selector_train = _sig("ewah_selector_train", _i32, [_vp, _vp, _u32, _u32, _vp, ctypes.POINTER(TrainConfig),
+                                                     ctypes.POINTER(_vp)])
+_selector_train_loss = _sig("ewah_selector_train_loss", ctypes.c_float, [_vp])
+_selector_predict = _sig("ewah_selector_predict", _i32, [_vp, _i32, _vp, _u32, _vp, _vp])
+SELECT_MLP, SELECT_RULES = 0, 1
 _mlp_create = _sig("ewah_mlp_create", _i32, [_u32, _u64, ctypes.POINTER(_vp)])
 _mlp_free = _sig("ewah_mlp_free", None, [_vp])
 _mlp_num_params = _sig("ewah_mlp_num_params", _u64, [_u32])
@@ -103,7 +122,10 @@ EXPORTED = ["ewah_init", "ewah_last_error", "ewah_register", "ewah_register_many
             "ewah_variant_code", "ewah_variant_code_ex", "ewah_default_variant", "ewah_batch_plan", "ewah_batch_run",
             "ewah_batch_set_variants", "ewah_batch_set_grid", "ewah_batch_free", "ewah_device_errors",
             "ewah_num_cus", "ewah_query_features", "ewah_batch_features", "ewah_batch_select",
-            "ewah_batch_get_variants", "ewah_mlp_create", "ewah_mlp_free", "ewah_mlp_num_params",
+            "ewah_batch_get_variants", "ewah_batch_time_queries", "ewah_batch_select_model",
+            "ewah_variant_code_full", "ewah_selector_load", "ewah_selector_save", "ewah_selector_free",
+            "ewah_selector_num_arms", "ewah_selector_arm_codes", "ewah_selector_train", "ewah_selector_train_loss",
+            "ewah_selector_predict", "ewah_mlp_create", "ewah_mlp_free", "ewah_mlp_num_params",
             "ewah_mlp_get_params", "ewah_mlp_set_params", "ewah_mlp_forward", "ewah_mlp_grad",
             "ewah_mlp_train_step", "ewah_mlp_last_error"]
 
@@ -140,7 +162,9 @@ def output_bound(n_bits: int, sum_input_words: int) -> int:
     return int(_output_bound(n_bits, sum_input_words))
 
 
-def variant_code(dense: bool, walk: int, litwalk: int, looped: bool = False) -> int:
+def variant_code(dense: bool, walk: int, litwalk: int, looped: bool = False, gate: int = 0) -> int:
+    if gate:
+        return int(_variant_code_full(1 if dense else 0, walk, litwalk, 1 if looped else 0, gate))
     if looped:
         return int(_variant_code_ex(1 if dense else 0, walk, litwalk, 1))
     return int(_variant_code(1 if dense else 0, walk, litwalk))
@@ -324,6 +348,16 @@ class Batch:
         a = self._codes
         _check(_batch_select(self._h, pred_ptr, len(a), a.ctypes.data, _stream_ptr(stream)), "batch_select")
 
+    def time_queries(self, reps: int = 2, stream=None) -> np.ndarray:
+        """Per-query busy time inside the batch (us), min over reps eager runs."""
+        out = np.zeros(self.nq, dtype=np.float32)
+        _check(_batch_time_queries(self._h, reps, out.ctypes.data, _stream_ptr(stream)), "batch_time_queries")
+        return out
+
+    def select_model(self, selector, mode: int = 0, stream=None):
+        """Features -> selector prediction -> per-query argmin into the batch (device, asynchronous)."""
+        _check(_batch_select_model(self._h, selector.handle, mode, _stream_ptr(stream)), "batch_select_model")
+
     def get_variants(self) -> np.ndarray:
         out = np.zeros(self.nq, dtype=np.uint32)
         _check(_batch_get_variants(self._h, out.ctypes.data), "batch_get_variants")
@@ -332,6 +366,56 @@ class Batch:
     def free(self):
         if self._h:
             _batch_free(self._h)
+            self._h = None
+
+
+class Selector:
+    """Handle of a library selector: learned cost model plus rule set (ewah_selector_*)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        self.n_arms = int(_selector_num_arms(handle))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @classmethod
+    def load(cls, path: str) -> "Selector":
+        h = _vp()
+        _check(_selector_load(os.fsencode(path), ctypes.byref(h)), "selector_load")
+        return cls(h)
+
+    @classmethod
+    def train(cls, feat, log2_time, arm_codes, epochs: int = 0, batch: int = 0, lr: float = 0.0,
+              seed: int = 0) -> "Selector":
+        F = np.ascontiguousarray(np.asarray(feat, dtype=np.float32))
+        Y = np.ascontiguousarray(np.asarray(log2_time, dtype=np.float32))
+        C = np.ascontiguousarray(np.asarray(arm_codes, dtype=np.uint32))
+        assert F.ndim == 2 and F.shape[1] == 16 and Y.shape == (F.shape[0], len(C))
+        cfg = TrainConfig(epochs, batch, lr, seed)
+        h = _vp()
+        _check(_selector_train(F.ctypes.data, Y.ctypes.data, F.shape[0], len(C), C.ctypes.data, ctypes.byref(cfg),
+                               ctypes.byref(h)), "selector_train")
+        return cls(h)
+
+    def save(self, path: str):
+        _check(_selector_save(self._h, os.fsencode(path)), "selector_save")
+
+    def arm_codes(self) -> np.ndarray:
+        out = np.zeros(self.n_arms, dtype=np.uint32)
+        _check(_selector_arm_codes(self._h, out.ctypes.data), "selector_arm_codes")
+        return out
+
+    def train_loss(self) -> float:
+        return float(_selector_train_loss(self._h))
+
+    def predict(self, feat_ptr: int, n: int, pred_ptr: int, mode: int = 0, stream=None):
+        _check(_selector_predict(self._h, mode, feat_ptr, n, pred_ptr, _stream_ptr(stream)), "selector_predict")
+
+    def free(self):
+        if self._h:
+            _selector_free(self._h)
             self._h = None
 
 

@@ -1,23 +1,20 @@
-"""Per-query kernel-variant selection.
+"""Per-query kernel-variant selection for the batched path.
 
 Every variant ("arm") computes the same canonical result; they differ in how
-the tile routine spends its work (dense carry-save rows or sparse ripple adds
-for whole-tile dirty runs; a binary or a unary per-row counter; how long a
-segment may be before it is split across a wavefront).  Three selectors share one interface:
+the tile routine spends its work: dense carry-save rows or sparse ripple adds
+for whole-tile dirty runs, a binary or a unary per-row counter, how long a
+segment may be before it is split across a wavefront, and when the per-group
+count bounds are worth counting.  The selector itself lives in the library
+(ewah_selector_*): a learned cost model (FP32 MLP trained by the library's own
+HIP kernels on timings the batched launch measures) and the paper-style rule set
+(least-squares running-time models of the forms of Section 8.1, smallest
+estimate taken as in hybrid H, Section 8.2).  This module names the arms,
+keeps the numpy definition of the features for tests, and wraps the three ways
+of choosing:
 
-  MLPSelector   learned cost model: features computed on the device from the
-                registration catalog, FP32 MLP (HIP kernels) predicting the
-                log-time of every arm, per-query argmin written straight into
-                the batch's device query records;
-  RuleSelector  paper-style rules: a running-time model per arm of the form
-                c1 * EWAHSize + c2 * EWAHSize * ln N + c3 * N * tiles + c4 * T *
-                EWAHSize, fitted by least squares to measured times (the
-                fitting procedure of Section 8.1), choosing the smallest
-                estimate (hybrid H, Section 8.2);
+  MLPSelector   learned cost model, features -> prediction -> argmin on the device;
+  RuleSelector  the rule set of the same model file, on the device;
   FixedSelector one arm for every query.
-
-Exhaustive timing (the oracle selector H_opt of Section 8.2) measures
-their regret; it lives in train_selector.py.
 """
 from __future__ import annotations
 
@@ -31,33 +28,39 @@ DEFAULT_MODEL = os.path.join(HERE, "selector_model.json")
 
 N_FEATURES = 16
 
-# Arms: (name, dense, walk, litwalk, looped).  All compute identical outputs.
+# Arms: (name, dense, walk, litwalk, looped, gate).  All compute identical outputs.
 #   sparse_*  bit-sliced binary counter, every dirty word added by ripple carry
 #             (the accumulator of BSTM, Section 5.3.1);
 #   hybrid_*  the same, with inputs whose dirty run covers a whole tile summed by
 #             a carry-save-adder tree (a sideways-sum circuit);
 #   looped_*  unary saturating counter with levels 1..T (the Looped recurrence,
-#             Section 6.2); taken when T <= bit length of N, else as sparse_*.
+#             Section 6.2); taken when T <= bit length of N, else as sparse_*;
+#   *_gate*   the per-group count bounds (RBMrg's second case, Section 6.4, inside a
+#             tile) counted always, never, or above 1.5x the mean bound instead of
+#             above 1.1x.
 ARMS = [
-    ("hybrid_w8", True, 8, 8, False),
-    ("sparse_w8", False, 8, 8, False),
-    ("hybrid_coop", True, 0, 0, False),
-    ("sparse_walk64", False, 64, 64, False),
-    ("hybrid_walk32", True, 32, 64, False),
-    ("hybrid_walk128", True, 128, 255, False),
-    ("looped_w8", False, 8, 8, True),
-    ("looped_coop", False, 0, 0, True),
+    ("hybrid_w8", True, 8, 8, False, 0),
+    ("sparse_w8", False, 8, 8, False, 0),
+    ("hybrid_coop", True, 0, 0, False, 0),
+    ("sparse_walk64", False, 64, 64, False, 0),
+    ("hybrid_walk32", True, 32, 64, False, 0),
+    ("hybrid_walk128", True, 128, 255, False, 0),
+    ("looped_w8", False, 8, 8, True, 0),
+    ("looped_coop", False, 0, 0, True, 0),
+    ("hybrid_w8_gate_always", True, 8, 8, False, 1),
+    ("hybrid_w8_gate_never", True, 8, 8, False, 2),
+    ("hybrid_w8_gate_1.5", True, 8, 8, False, 3),
 ]
 
 
-def arm_codes():
+def arm_codes(arms=None):
     from . import ewahthr as E
-    return [E.variant_code(d, w, l, looped=lp) for (_, d, w, l, lp) in ARMS]
+    return [E.variant_code(d, w, l, looped=lp, gate=g) for (_, d, w, l, lp, g) in (arms or ARMS)]
 
 
 def features_host(queries, stats, n_bits: int) -> np.ndarray:
     """Reference definition of the 16 features in numpy (the device kernel computes
-    the same in FP32; used by tests and the rule set)."""
+    the same in FP32; used by tests)."""
     nw = np.array([s["n_words"] for s in stats], dtype=np.float64)
     lit = np.array([s["n_literals"] for s in stats], dtype=np.float64)
     pop = np.array([s["popcount"] for s in stats], dtype=np.float64)
@@ -85,7 +88,8 @@ def features_host(queries, stats, n_bits: int) -> np.ndarray:
 
 
 def rule_regressors(feat: np.ndarray) -> np.ndarray:
-    """Regressors of the paper-style running-time model, from the features."""
+    """Regressors of the paper-style running-time model, from the features (numpy
+    statement of the library's definition, for tests)."""
     ewah = 2.0 ** feat[:, 10] - 1.0            # total compressed words (EWAHSize / 8)
     N = 2.0 ** feat[:, 0]
     T = 2.0 ** feat[:, 1]
@@ -97,106 +101,52 @@ def rule_regressors(feat: np.ndarray) -> np.ndarray:
 class FixedSelector:
     kind = "fixed"
 
-    def __init__(self, variant: int = 0, grid: int = 0):
+    def __init__(self, variant: int = 0):
         self.variant = variant
-        self.grid = grid
 
-    def choose_host(self, feat):
-        return np.full(len(feat), self.variant, dtype=np.uint32)
-
-    def apply(self, batch, pool, queries, n_bits, stream=None):
-        batch.set_variants(np.full(len(queries), self.variant, dtype=np.uint32))
+    def apply(self, batch, stream=None):
+        batch.set_variants(np.full(batch.nq, self.variant, dtype=np.uint32))
         return f"fixed:{self.variant:#x}"
 
 
-class RuleSelector:
-    kind = "rules"
+class _LibSelector:
+    mode = 0
+    kind = ""
 
-    def __init__(self, coef: np.ndarray, codes, grid: int = 0):
-        self.coef = np.asarray(coef, dtype=np.float64)     # [n_regressors, K]
-        self.codes = [int(c) for c in codes]
-        self.grid = grid
+    def __init__(self, lib_selector):
+        self.sel = lib_selector
+        self.codes = [int(c) for c in lib_selector.arm_codes()]
 
-    @staticmethod
-    def fit(feat: np.ndarray, times: np.ndarray) -> np.ndarray:
-        """Least squares through the origin per arm (Section 8.1): times [n, K] in microseconds."""
-        X = rule_regressors(feat)
-        coef = np.zeros((X.shape[1], times.shape[1]))
-        for k in range(times.shape[1]):
-            coef[:, k], *_ = np.linalg.lstsq(X, times[:, k], rcond=None)
-        return coef
+    def apply(self, batch, stream=None):
+        """Features -> prediction -> argmin, on the device; the choice lands in the batch's
+        query records (one call per plan: a batch's features do not change)."""
+        batch.select_model(self.sel, self.mode, stream)
+        return self.kind
 
-    def predict(self, feat):
-        return rule_regressors(feat) @ self.coef
-
-    def choose_arm(self, feat):
-        return np.argmin(self.predict(feat), axis=1)
-
-    def choose_host(self, feat):
-        return np.asarray([self.codes[j] for j in self.choose_arm(feat)], dtype=np.uint32)
-
-    def apply(self, batch, pool, queries, n_bits, stream=None):
-        import torch
-        feat = torch.zeros((len(queries), N_FEATURES), dtype=torch.float32, device="cuda")
-        batch.features(feat.data_ptr(), stream)
-        batch.set_variants(self.choose_host(feat.cpu().numpy().astype(np.float64)))
-        return "rules"
+    def free(self):
+        self.sel.free()
 
 
-class MLPSelector:
+class MLPSelector(_LibSelector):
+    mode = 0
     kind = "mlp"
 
-    def __init__(self, model: dict):
-        self.model = model
-        self.grid = int(model.get("grid", 0))
-        self.codes = [int(c) for c in model["arm_codes"]]
-        self._pred = None
 
-    def predictor(self):
-        if self._pred is None:
-            from .mlp import Predictor
-            self._pred = Predictor(self.model)
-        return self._pred
-
-    def prepare(self, batch, nq: int):
-        """Device buffers for per-step selection on one batch."""
-        import torch
-        self._batch = batch
-        self._nq = nq
-        self._feat = torch.zeros((nq, N_FEATURES), dtype=torch.float32, device="cuda")
-        self._predbuf = torch.zeros((nq, len(self.codes)), dtype=torch.float32, device="cuda")
-        self.predictor()
-
-    def apply_device(self, stream=None):
-        """Features -> MLP -> argmin, all on the device and asynchronous; the choice lands in the
-        batch's query records, read by the next run of the batch."""
-        self._batch.features(self._feat.data_ptr(), stream)
-        self._pred.forward(self._feat.data_ptr(), self._nq, self._predbuf.data_ptr(), stream)
-        self._batch.select_async(self._predbuf.data_ptr(), stream)
-
-    def apply(self, batch, pool, queries, n_bits, stream=None):
-        self.prepare(batch, len(queries))
-        batch.set_arm_codes(self.codes)
-        self.apply_device(stream)
-        return "mlp"
-
-    def choose_device_arms(self, feat_ptr: int, n: int):
-        import torch
-        pred = torch.zeros((n, len(self.codes)), dtype=torch.float32, device="cuda")
-        self.predictor().forward(feat_ptr, n, pred.data_ptr())
-        return pred.argmin(dim=1).cpu().numpy()
+class RuleSelector(_LibSelector):
+    mode = 1
+    kind = "rules"
 
 
-def load_selector(path: str | None = None):
+def load_selector(path: str | None = None, kind: str = "mlp"):
+    """The library selector of a model file (default: the committed model), or the default
+    variant for every query when there is no model file."""
+    from . import ewahthr as E
     p = path or DEFAULT_MODEL
-    if os.path.exists(p):
-        with open(p) as f:
-            m = json.load(f)
-        kind = m.get("kind", "mlp")
-        if kind == "mlp":
-            return MLPSelector(m)
-        if kind == "rules":
-            return RuleSelector(np.asarray(m["coef"]), m["arm_codes"], m.get("grid", 0))
-        if kind == "fixed":
-            return FixedSelector(int(m.get("variant", 0)), int(m.get("grid", 0)))
-    return FixedSelector(0, 0)
+    if not os.path.exists(p):
+        return FixedSelector(0)
+    with open(p) as f:
+        m = json.load(f)
+    if m.get("kind", "mlp") == "fixed":
+        return FixedSelector(int(m.get("variant", 0)))
+    sel = E.Selector.load(p)
+    return RuleSelector(sel) if kind == "rules" else MLPSelector(sel)

@@ -4,8 +4,9 @@
 * the pure host entry points (output bound, variant codes) follow their documented
   definitions; the bound is checked against true canonical output sizes computed by
   the oracle;
-* selector host logic: the feature definition, the rule-set least-squares fit and
-  the exact folding of input standardisation into the first MLP layer.
+* selector host logic: the feature definition, the library's model-file reader and
+  writer, and its exact folding of input standardisation into the first MLP layer
+  (the rule-set fit is checked on the GPU, since training runs there).
 
 No GPU work is started here.
 """
@@ -103,36 +104,61 @@ def test_features_definition_on_known_stats():
     assert np.isfinite(f[1]).all() and np.isclose(f[1][6], np.log2(1e-9))
 
 
-def test_rule_fit_recovers_planted_coefficients():
-    from paper_1402_4466_amd import selector as S
-    rng = np.random.default_rng(3)
-    n = 400
-    feat = np.zeros((n, S.N_FEATURES))
-    feat[:, 0] = rng.uniform(1, 8, n)                 # log2 N
-    feat[:, 1] = feat[:, 0] * rng.uniform(0, 1, n)    # log2 T
-    feat[:, 10] = rng.uniform(8, 20, n)               # log2 words
-    feat[:, 12] = rng.uniform(0, 1, n)
-    feat[:, 13] = rng.uniform(16, 24, n)
-    X = S.rule_regressors(feat)
-    coef = rng.uniform(0.1, 2.0, (X.shape[1], 3))
-    times = X @ coef
-    fit = S.RuleSelector.fit(feat, times)
-    assert np.allclose(fit, coef, rtol=1e-6)
-    sel = S.RuleSelector(fit, [11, 22, 33])
-    assert (sel.choose_arm(feat) == np.argmin(times, axis=1)).all()
-
-
-def test_standardisation_fold_is_exact():
-    from paper_1402_4466_amd import mlp as M
+def test_standardisation_fold_is_exact(E):
+    """The library folds the features' standardisation into the first layer
+    (W1' = W1 / sigma, b1' = b1 - (mu / sigma) W1) when a model file has no folded
+    parameters; the saved folded network on raw features equals the raw network on
+    standardised features (FP64 reference forward)."""
+    import json
+    import tempfile
     rng = np.random.default_rng(4)
     k = 5
-    n_par = M.NI * M.H + M.H + M.H * M.H + M.H + M.H * k + k
+    n_par = int(E._mlp_num_params(k))
     p = rng.normal(0, 0.3, n_par)
-    X = rng.normal(3.0, 2.0, (200, M.NI))
+    mu = rng.normal(3.0, 2.0, 16)
+    sd = rng.uniform(0.5, 3.0, 16)
+    mu[-1], sd[-1] = 0.0, 1.0
+    coef = rng.uniform(0.0, 1.0, (5, k))
+    with tempfile.TemporaryDirectory() as d:
+        src, dst = os.path.join(d, "m.json"), os.path.join(d, "m2.json")
+        with open(src, "w") as f:
+            json.dump({"kind": "mlp", "n_out": k, "arm_codes": [11, 22, 33, 44, 55], "mu": mu.tolist(),
+                       "sigma": sd.tolist(), "params_raw": p.tolist(), "rules_coef": coef.tolist(),
+                       "eval": {"ignored": [1, {"s": "x\u00e9"}]}}, f)
+        sel = E.Selector.load(src)
+        assert sel.n_arms == k and sel.arm_codes().tolist() == [11, 22, 33, 44, 55]
+        sel.save(dst)
+        sel.free()
+        with open(dst) as f:
+            m2 = json.load(f)
+    X = rng.normal(3.0, 2.0, (200, 16))
     X[:, -1] = 1.0
-    mu, sd = M.standardiser(X)
-    assert mu[-1] == 0.0 and sd[-1] == 1.0
     Xs = (X - mu) / sd
-    y_std, _ = R.forward(p, Xs, k)
-    y_fold, _ = R.forward(M.fold_standardisation(p, k, mu, sd).astype(np.float64), X, k)
+    y_std, _ = R.forward(np.asarray(m2["params_raw"]), Xs, k)
+    y_fold, _ = R.forward(np.asarray(m2["params_folded"]), X, k)
     assert np.allclose(y_std, y_fold, rtol=1e-5, atol=1e-5)
+    assert np.allclose(np.asarray(m2["rules_coef"]).ravel(), coef.ravel())
+
+
+def test_selector_model_errors(E):
+    import json
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        bad = os.path.join(d, "bad.json")
+        for body in ('{"kind": "mlp", "arm_codes": [1, 2]', '{"kind": "mlp", "arm_codes": [1, 2], "mu": [0]}',
+                     '[1, 2, 3]'):
+            with open(bad, "w") as f:
+                f.write(body)
+            with pytest.raises(E.EwahError) as e:
+                E.Selector.load(bad)
+            assert e.value.code == E.EFORMAT, body
+        with pytest.raises(E.EwahError) as e:
+            E.Selector.load(os.path.join(d, "missing.json"))
+        assert e.value.code == E.EINVAL
+        ok = os.path.join(d, "ok.json")
+        with open(ok, "w") as f:
+            json.dump({"arm_codes": [7], "mu": [0.0] * 16, "sigma": [1.0] * 16,
+                       "params_raw": [0.0] * int(E._mlp_num_params(1))}, f)
+        sel = E.Selector.load(ok)
+        assert sel.n_arms == 1
+        sel.free()

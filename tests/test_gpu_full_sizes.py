@@ -4,12 +4,8 @@
 * N=64 Markov bitmaps over 2^24 rows and N=1024 Zipf-density bitmaps over 2^26
   rows: every output word of every threshold compared with the oracle (the
   oracle finishes these in seconds);
-* the batched workload (pool of 10,000 bitmaps over 2^22 rows, 4,096 queries)
-  in the benchmark's launch: learned variant selection on the device, the tuned
-  persistent grid, one graph launch.  Sampled queries are compared whole with
-  the oracle; every other output is checked for properties that hold at any
-  size: it decodes to exactly U words, it is canonical (re-encoding it gives it
-  back), and its length respects the output bound;
+* (the full-size batched workloads are compared output by output in
+  test_gpu_headline.py);
 * degenerate shapes and the input-count limit (N = 4095: threshold, the unary counter at its
   12 levels, the 4,096-bin count histogram, opt-threshold and a symmetric function).
 """
@@ -59,50 +55,6 @@ def test_config2_full(G):
 def test_config3_full(G):
     E = G.lib()
     _plain_all_T(G, D.config3(), [0, E.variant_code(False, 8, 8, looped=True)])
-
-
-def test_batched_full_size_sampled(G):
-    import torch
-    E = G.lib()
-    from paper_1402_4466_amd import autotune as A
-    from paper_1402_4466_amd import selector as S
-    n_bits = 1 << 22
-    U = n_bits // 64
-    pool, _ = D.config4_pool(10_000)
-    qs = D.queries(D.SEED_BASE + 4, 4096, 10_000, 2, 256)
-    bms = E.register_many(pool, n_bits)
-    nw = np.array([len(s) for s in pool], dtype=np.int64)
-    caps = [E.output_bound(n_bits, int(nw[q.idx].sum())) for q in qs]
-    offs = np.concatenate([[0], np.cumsum(caps)])
-    out = torch.zeros(int(offs[-1]), dtype=torch.int64, device="cuda")
-    out_n = torch.zeros(len(qs), dtype=torch.int64, device="cuda")
-    batch = E.Batch(bms, [(q.idx, q.T) for q in qs], [out.data_ptr() + 8 * int(o) for o in offs[:-1]], caps,
-                    [out_n.data_ptr() + 8 * i for i in range(len(qs))], grid=E.num_cus(), use_graph=True)
-    sel = S.load_selector()
-    kind = sel.apply(batch, bms, qs, n_bits)
-    tuned = A.lookup(f"c4_q{len(qs)}_pool{len(pool)}_{kind}")
-    batch.set_grid(int(tuned["grid"]) if tuned else E.num_cus())
-    batch.run()
-    torch.cuda.synchronize()
-    assert E.device_errors() == 0
-    ns = out_n.cpu().numpy()
-    host = out.cpu().numpy().view(np.uint64)
-    rng = np.random.default_rng(2024)
-    sample = set(rng.choice(len(qs), 12, replace=False).tolist()) | {int(np.argmax([len(q.idx) for q in qs]))}
-    for i, q in enumerate(qs):
-        got = host[offs[i]:offs[i] + ns[i]]
-        assert 0 < ns[i] <= caps[i], (i, ns[i], caps[i])
-        if i in sample:
-            want, _ = O.threshold([pool[j] for j in q.idx], n_bits, q.T, want_hist=False)
-            _say(f"query {i}: N={len(q.idx)} T={q.T}: {len(got)} words (oracle {len(want)})")
-            assert np.array_equal(got, want), i
-        else:
-            dense = O.decode(got, n_bits)
-            assert len(dense) == U
-            assert np.array_equal(O.encode(dense, n_bits), got), i
-    batch.free()
-    for b in bms:
-        b.release()
 
 
 def test_degenerate_shapes(G):

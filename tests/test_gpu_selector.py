@@ -1,6 +1,7 @@
 """GPU tests of the learned selection path: MLP kernels against the FP64
 oracle, device features against their numpy definition, device argmin
 selection, and bit-exact results whatever the selection."""
+import os
 import sys
 
 import numpy as np
@@ -57,25 +58,55 @@ def test_mlp_forward_and_gradient_match_fp64(env):
     net.free()
 
 
-def test_mlp_training_reduces_loss(env):
+def test_selector_training_fits_and_rules_recover_planted_costs(env):
+    """ewah_selector_train: the network, trained by the library's kernels on the GPU, fits
+    smooth relative costs; the rule set fitted on the same labels recovers planted
+    coefficients of the Section 8.1 model forms; the arm with the smallest prediction is
+    the planted cheapest arm for nearly every sample."""
     E, torch = env
-    k = 4
+    from paper_1402_4466_amd import selector as S
     rng = np.random.default_rng(11)
-    n = 4096
-    x = rng.normal(0, 1, (n, 16))
-    x[:, -1] = 1.0
-    A = rng.normal(0, 0.5, (16, k))
-    y = np.tanh(x @ A) + 0.01 * rng.normal(0, 1, (n, k))
-    from paper_1402_4466_amd import mlp as M
-    model, hist = M.train(x, y, epochs=30, batch=256, lr=3e-3, seed=2)
-    assert hist[-1] < 0.2 * hist[0], hist
-    # folded weights give the same predictions on raw inputs as the trained net on standardised inputs
-    mu, sd = np.asarray(model["mu"]), np.asarray(model["sigma"])
-    xs = (x - mu) / sd
-    xs[:, -1] = 1.0
-    y_std, _ = R.forward(np.asarray(model["params_raw"]), xs, k)
-    y_fold, _ = R.forward(np.asarray(model["params_folded"]), x, k)
-    assert np.allclose(y_std, y_fold, rtol=1e-4, atol=1e-4)
+    n, k = 4096, 3
+    feat = np.zeros((n, 16))
+    feat[:, 0] = rng.uniform(1, 8, n)                 # log2 N
+    feat[:, 1] = feat[:, 0] * rng.uniform(0, 1, n)    # log2 T
+    feat[:, 10] = rng.uniform(8, 20, n)               # log2 words
+    feat[:, 12] = rng.uniform(0, 1, n)
+    feat[:, 13] = rng.uniform(16, 24, n)
+    feat[:, 15] = 1.0
+    X = S.rule_regressors(feat)
+    coef = rng.uniform(0.1, 2.0, (X.shape[1], k))
+    t_us = X @ coef
+    sel = E.Selector.train(feat.astype(np.float32), np.log2(t_us).astype(np.float32), [101, 102, 103],
+                           epochs=40, batch=256, lr=3e-3, seed=2)
+    try:
+        import json
+        import tempfile
+        with tempfile.TemporaryDirectory() as d:
+            path = os.path.join(d, "m.json")
+            sel.save(path)
+            with open(path) as f:
+                m = json.load(f)
+        fit = np.asarray(m["rules_coef"]).reshape(5, k)
+        assert np.allclose(fit, coef, rtol=1e-3), (fit, coef)
+        # predictions on the device: relative log-times from the network, microseconds from the rules
+        fd = torch.as_tensor(feat, dtype=torch.float32, device="cuda").contiguous()
+        pm = torch.zeros((n, k), dtype=torch.float32, device="cuda")
+        pr = torch.zeros((n, k), dtype=torch.float32, device="cuda")
+        sel.predict(fd.data_ptr(), n, pm.data_ptr(), E.SELECT_MLP)
+        sel.predict(fd.data_ptr(), n, pr.data_ptr(), E.SELECT_RULES)
+        torch.cuda.synchronize()
+        L = np.log2(t_us)
+        rel = L - L.mean(axis=1, keepdims=True)
+        err = np.abs(pm.cpu().numpy() - rel).mean()
+        _say(f"selector training: loss {sel.train_loss():.4f}, mean |error| {err:.4f} (targets spread "
+             f"{np.abs(rel).mean():.3f})")
+        assert err < 0.25 * np.abs(rel).mean()
+        assert np.allclose(pr.cpu().numpy(), t_us, rtol=1e-3)
+        agree = np.mean(pm.cpu().numpy().argmin(axis=1) == t_us.argmin(axis=1))
+        assert agree > 0.9, agree
+    finally:
+        sel.free()
 
 
 def test_device_features_match_definition(env):
@@ -98,7 +129,8 @@ def test_device_features_match_definition(env):
 
 def test_learned_selection_keeps_results_bit_exact(env):
     E, torch = env
-    from paper_1402_4466_amd import mlp as M
+    import json
+    import tempfile
     from paper_1402_4466_amd import selector as S
     from tests import gpu_util as G
     n_bits = 2 * 65536 + 77
@@ -111,26 +143,36 @@ def test_learned_selection_keeps_results_bit_exact(env):
     batch = E.Batch(bms, [(q.idx, q.T) for q in qs], [o[0].data_ptr() for o in outs], [o[2] for o in outs],
                     [o[1].data_ptr() for o in outs])
     codes = S.arm_codes()
-    # an untrained (random) network: any selection must give identical outputs
+    # an untrained (random) network and rule set: any selection must give identical outputs
     rng = np.random.default_rng(5)
-    model = {"kind": "mlp", "n_out": len(codes), "arm_codes": codes,
-             "params_folded": rng.normal(0, 0.3, M.NI * M.H + M.H + M.H * M.H + M.H + M.H * len(codes) + len(codes)).tolist()}
-    sel = S.MLPSelector(model)
-    sel.apply(batch, bms, qs, n_bits)
-    chosen = batch.get_variants()
-    assert set(chosen.tolist()) <= set(codes)
-    # argmin agrees with the predictions
+    k = len(codes)
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "random.json")
+        with open(path, "w") as f:
+            json.dump({"kind": "mlp", "n_out": k, "arm_codes": codes, "mu": [0.0] * 16, "sigma": [1.0] * 16,
+                       "params_raw": rng.normal(0, 0.3, int(E._mlp_num_params(k))).tolist(),
+                       "rules_coef": rng.uniform(-1, 1, (5, k)).tolist()}, f)
+        sel = E.Selector.load(path)
     feat = torch.zeros((len(qs), 16), dtype=torch.float32, device="cuda")
     batch.features(feat.data_ptr())
-    arms = sel.choose_device_arms(feat.data_ptr(), len(qs))
-    assert [codes[a] for a in arms] == chosen.tolist()
-    batch.run()
-    torch.cuda.synchronize()
-    for i, q in enumerate(qs):
-        want, _ = O.threshold([pool[j] for j in q.idx], n_bits, q.T, want_hist=False)
-        assert np.array_equal(G.fetch(outs[i][0], outs[i][1]), want)
+    pred = torch.zeros((len(qs), k), dtype=torch.float32, device="cuda")
+    for mode in (E.SELECT_MLP, E.SELECT_RULES):
+        batch.select_model(sel, mode)
+        chosen = batch.get_variants()
+        assert set(chosen.tolist()) <= set(codes)
+        # the argmin agrees with the predictions
+        sel.predict(feat.data_ptr(), len(qs), pred.data_ptr(), mode)
+        arms = pred.argmin(dim=1).cpu().numpy()
+        assert [codes[a] for a in arms] == chosen.tolist()
+        for o in outs:
+            o[0].fill_(-1)
+        batch.run()
+        torch.cuda.synchronize()
+        for i, q in enumerate(qs):
+            want, _ = O.threshold([pool[j] for j in q.idx], n_bits, q.T, want_hist=False)
+            assert np.array_equal(G.fetch(outs[i][0], outs[i][1]), want)
     assert E.device_errors() == 0
     batch.free()
-    sel.predictor().free()
+    sel.free()
     for b in bms:
         b.release()

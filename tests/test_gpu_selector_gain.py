@@ -1,0 +1,144 @@
+"""What the trained network gains over the method without it (needs an MI355X).
+
+The committed model was trained on the training queries of the selector workload and of
+the Many-Criteria / Similarity(n) workloads (disjoint seeds from the held-out sets used
+here).  On held-out batches, every query is labelled with its busy time inside the
+batched launch under each arm (min of 3 runs); the learned choice (features -> MLP ->
+argmin on the device), the paper-style rule set (Section 8.1 model forms, least squares),
+the library default for every query (the method without the network) and the exhaustive
+optimum H_opt (Section 8.2) are then compared:
+* by busy-time regret against H_opt (sum t(chosen) / sum t(best) - 1) and the paper's
+  20 % view (Section 7.5);
+* by the whole launch time of the batch with each choice (min of repeated graph
+  launches, interleaved so that drift hits every choice alike).
+"""
+import json
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1402_4466_amd import datagen as D
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    from tests import gpu_util
+    E = gpu_util.lib()
+    from paper_1402_4466_amd import selector as S
+    sel = S.load_selector()
+    assert isinstance(sel, S.MLPSelector), "no trained model committed"
+    yield E, S, sel
+    sel.free()
+
+
+def _compare(E, S, sel, pb, reps_label=3, rounds=3, launches=3):
+    import torch
+    codes = sel.codes
+    nq = len(pb.queries)
+    busy = np.zeros((nq, len(codes)))
+    for k, c in enumerate(codes):
+        pb.batch.set_variants(np.full(nq, c, dtype=np.uint32))
+        busy[:, k] = pb.batch.time_queries(reps_label)
+    busy = np.maximum(busy, 1e-3)
+    default = np.full(nq, E.default_variant(), dtype=np.uint32)
+    sel.apply(pb.batch)
+    mlp = pb.batch.get_variants()
+    S.RuleSelector(sel.sel).apply(pb.batch)
+    rules = pb.batch.get_variants()
+    exhaustive = np.asarray(codes, dtype=np.uint32)[busy.argmin(axis=1)]
+    ways = {"default": default, "rules": rules, "mlp": mlp, "exhaustive": exhaustive}
+    col = {c: k for k, c in enumerate(codes)}
+    assert all(int(v) in col for w in ways.values() for v in w), "a choice outside the arm set"
+    best = busy.min(axis=1)
+    rep = {"queries": nq}
+    for name, v in ways.items():
+        t = busy[np.arange(nq), [col[int(x)] for x in v]]
+        rep[f"{name}_busy_regret"] = round(float(t.sum() / best.sum() - 1.0), 5)
+        rep[f"{name}_within_20pct"] = round(float(np.mean(t <= 1.25 * best)), 4)
+    ms = {name: float("inf") for name in ways}
+    for _ in range(rounds):
+        for name, v in ways.items():
+            pb.batch.set_variants(v)
+            pb.run()
+            torch.cuda.synchronize()
+            for _ in range(launches):
+                s = torch.cuda.Event(enable_timing=True)
+                e = torch.cuda.Event(enable_timing=True)
+                s.record()
+                pb.run()
+                e.record()
+                e.synchronize()
+                ms[name] = min(ms[name], s.elapsed_time(e))
+    for name in ways:
+        rep[f"{name}_batch_ms"] = round(ms[name], 4)
+    assert E.device_errors() == 0
+    return rep
+
+
+def test_learned_selector_gain_on_heldout_pooled_batch(env):
+    E, S, sel = env
+    from paper_1402_4466_amd.workload import PooledBatch
+    n_bits = 1 << 22
+    pool, _ = D.config4_pool(10_000, n_bits)
+    bms = E.register_many(pool, n_bits)
+    nw = np.array([len(s) for s in pool], dtype=np.int64)
+    te = D.config5_queries(10_000, 0, 10_000)[1]
+    pb = PooledBatch(bms, nw, te, n_bits)
+    try:
+        rep = _compare(E, S, sel, pb)
+    finally:
+        pb.free()
+        for b in bms:
+            b.release()
+    _say("held-out pooled batch: " + json.dumps(rep))
+    # the network picks better per query than the method without it and than the rule set
+    assert rep["mlp_busy_regret"] < 0.75 * rep["default_busy_regret"], rep
+    assert rep["mlp_busy_regret"] <= rep["rules_busy_regret"], rep
+    # and the launch of the whole batch is faster with its choice
+    assert rep["mlp_batch_ms"] < rep["default_batch_ms"], rep
+
+
+def test_learned_selector_gain_on_heldout_index_batches(env):
+    E, S, sel = env
+    import torch
+    from paper_1402_4466_amd.datagen import Query
+    from paper_1402_4466_amd.datagen import index as DI
+    from paper_1402_4466_amd.workload import PooledBatch
+    tot = {"default": 0.0, "mlp": 0.0, "rules": 0.0, "exhaustive": 0.0}
+    reg = {}
+    for sh in DI.SHAPE_NAMES:
+        ix = DI.build_index(DI.table(sh))
+        bms = E.register_many(ix.streams, ix.n_bits)
+        cap = E.output_bound(ix.n_bits, 1 << 40)
+        o = torch.zeros(cap, dtype=torch.int64, device="cuda")
+        on = torch.zeros(1, dtype=torch.int64, device="cuda")
+        no = DI.SHAPES[sh]["no"]
+        s0 = D.SEED_BASE + 42             # the held-out seeds of the training driver
+        raw = (DI.many_criteria({sh: ix}, 500, seed=s0 + 10 * no, shapes=(sh,)) +
+               DI.similarity({sh: ix}, 500, seed=s0 + 1 + 10 * no, shapes=(sh,)))
+        qs = []
+        for q in raw:
+            T = q.settle(E.opt_threshold([bms[b] for b in q.idx], 1, o.data_ptr(), cap, on.data_ptr()))
+            if T is not None:
+                qs.append(Query(q.idx, T))
+        pb = PooledBatch(bms, ix.n_words, qs, ix.n_bits)
+        try:
+            rep = _compare(E, S, sel, pb)
+        finally:
+            pb.free()
+            for b in bms:
+                b.release()
+        _say(f"held-out {sh} batch: " + json.dumps(rep))
+        for k in tot:
+            tot[k] += rep[f"{k}_batch_ms"]
+        reg[sh] = rep
+        assert rep["mlp_busy_regret"] < rep["default_busy_regret"], (sh, rep)
+    _say(f"held-out index batches, summed launch times: {json.dumps(tot)}")
+    assert tot["mlp"] < tot["default"], tot

@@ -5,7 +5,8 @@ Output row i is f[c_i] (c_i = inputs with row i set), f a table over 0..N
 compared word for word with the oracle on the same seeded inputs: several
 tiles and a ragged tail, word-level (N <= 256) and 4-word-group (N > 256)
 bounds, tables whose first value is 1 (groups settled as ones), parity, constant
-tables, the largest table accepted (8 runs of ones) and the rejection of others.
+tables, eight runs of ones (the largest that goes through run ends), and general
+tables of many runs (looked up per row) at N = 20, 64, 300 and 4095.
 """
 import os
 import re
@@ -55,6 +56,10 @@ def _tables(n, rng):
     }
     if n >= 16:   # eight runs of ones: counts 1, 3, ..., 15
         tabs["eight_runs"] = [1 if c < 16 and c % 2 == 1 else 0 for c in range(n + 1)]
+    if n >= 18:   # nine runs: looked up per row
+        tabs["nine_runs"] = [1 if c < 18 and c % 2 == 1 else 0 for c in range(n + 1)]
+    tabs["mod3"] = [1 if c % 3 == 0 else 0 for c in range(n + 1)]
+    tabs["random"] = [int(v) for v in rng.integers(0, 2, n + 1)]
     return tabs
 
 
@@ -103,28 +108,49 @@ def test_at_most_and_ranges_with_settled_groups(G):
     assert E.device_errors() == 0
 
 
-def test_rejected_tables(G):
+def test_general_tables_and_table_length(G):
     E = G.lib()
     n_bits = 1000
     n = 20
-    streams = D.bitmaps(D.IID, np.full(n, 0.1), 0.0, n_bits, [D.key(8080, k) for k in range(n)])
+    streams = D.bitmaps(D.IID, np.full(n, 0.3), 0.0, n_bits, [D.key(8080, k) for k in range(n)])
     bms = G.register(streams, n_bits)
     try:
         out, out_n, cap = G.alloc_out(n_bits, sum(b.n_words for b in bms))
-        nine = [0] * (n + 1)
-        for j in range(9):
-            nine[2 * j] = 1   # nine runs of ones, not parity
-        with pytest.raises(E.EwahError) as e:
-            E.symmetric(bms, nine, out.data_ptr(), cap, out_n.data_ptr())
-        assert e.value.code == E.EINVAL
         with pytest.raises(E.EwahError) as e:
             E.symmetric(bms, [1] * n, out.data_ptr(), cap, out_n.data_ptr())   # one entry short
         assert e.value.code == E.EINVAL
-        # eight runs are accepted
-        eight = [0] * (n + 1)
+        eight, nine = [0] * (n + 1), [0] * (n + 1)
         for j in range(8):
             eight[2 * j] = 1
-        assert np.array_equal(_gpu_symmetric(G, bms, eight), O.symmetric(streams, n_bits, eight))
+        for j in range(9):
+            nine[2 * j] = 1   # nine runs of ones, not parity
+        for f in (eight, nine):
+            assert np.array_equal(_gpu_symmetric(G, bms, f), O.symmetric(streams, n_bits, f))
+    finally:
+        for b in bms:
+            b.release()
+    assert E.device_errors() == 0
+
+
+@pytest.mark.parametrize("n,n_bits,seed", [(64, 3 * TW_ROWS + 5001, 71), (300, 2 * TW_ROWS + 99, 72),
+                                           (4095, TW_ROWS + 777, 73)])
+def test_many_run_tables_against_oracle(G, n, n_bits, seed):
+    """Tables with many runs of counts giving 1 (random, counts divisible by 3, every
+    count but one), including f(0) = 1, against the oracle."""
+    E = G.lib()
+    rng = np.random.default_rng(seed)
+    dens = rng.uniform(0.01, 0.5, n)
+    streams = D.bitmaps(D.MARKOV, 16.0, 16.0 * (1.0 - dens) / dens, n_bits, [D.key(seed, k) for k in range(n)])
+    bms = G.register(streams, n_bits)
+    try:
+        tabs = [[int(v) for v in rng.integers(0, 2, n + 1)] for _ in range(2)]
+        tabs.append([1 if c % 3 == 0 else 0 for c in range(n + 1)])
+        k = int(rng.integers(1, n))
+        tabs.append([0 if c == k else 1 for c in range(n + 1)])
+        for f in tabs:
+            want = O.symmetric(streams, n_bits, f)
+            got = _gpu_symmetric(G, bms, f)
+            assert np.array_equal(got, want), (n, n_bits, f[:20])
     finally:
         for b in bms:
             b.release()
