@@ -725,6 +725,31 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     }
     const bool prune = pm.any();
 
+    // ---- settled batched tile: every output word of the tile is one fill, so its run
+    // structure is known without compare and encode (one head at the tile's first word,
+    // nothing staged; the placement pass writes the marker).  mode comes from LDS counters
+    // read after the last barrier, the same for every wavefront, and the exit is taken
+    // here, outside every loop that holds a barrier, so all wavefronts leave together.
+    // An all-ones tile holding the last, partial word is excluded: that word is a literal.
+    if constexpr (STAGED && !GENERAL && !MAXC && !HIST) {
+        const uint32_t umode = (uint32_t)__builtin_amdgcn_readfirstlane((int)mode);
+        if (umode == 2u || (umode == 1u && !(tE == U && q.tail_bits))) {
+            if (tid == 0) {
+                const uint32_t c = umode == 1u ? 1u : 0u;
+                Agg A;
+                A.n = 1;
+                A.lh_pos = tS;
+                A.lh_out = 0;
+                A.bits = c | (c << 2) | (1u << 4) | (c << 5);
+                EWT_GLOBAL TileState* st = gp(q.state);
+                st[t].head[0] = 0ull;
+                st[t].head[1] = 1ull << 16;
+                agg_publish(st[t].local, A, epoch);
+            }
+            return;
+        }
+    }
+
     // ---- decode and count
     if (mode == 0) {
         for (uint32_t kb = 0; kb < N; kb += BLOCK) {
