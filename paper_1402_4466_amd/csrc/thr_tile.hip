@@ -424,16 +424,21 @@ __device__ __forceinline__ uint4 window_entry(const uint64_t* words, const uint4
 // Reads the list entries of windows [w0, min(w0 + WIN_BATCH, we)) (lane g holds
 // entry g), fetches the skip-index entries of aligned windows (lane g) and
 // issues the data loads of all of them; empty slots read nothing and add nothing.
-__device__ __forceinline__ void issue_batch(const uint4* win, uint32_t w0, uint32_t we, int lane, uint4& sk,
-                                            uint64_t (&v)[WIN_BATCH], uint32_t (&fl)[WIN_BATCH]) {
+__device__ __forceinline__ void issue_batch(const uint4* win, uint32_t w0, uint32_t we, int lane, const void* dummy,
+                                            uint4& sk, uint32_t& dz, uint64_t& alm, uint64_t (&v)[WIN_BATCH],
+                                            uint32_t (&fl)[WIN_BATCH]) {
     const uint32_t nb = min((uint32_t)WIN_BATCH, we - w0);
     uint4 d = make_uint4(0u, 0u, 0u, 0u);
     if ((uint32_t)lane < nb) d = win[w0 + (uint32_t)lane];
-    // skip-index entry of an aligned window; a dirty block has no markers and its
-    // first word at position d.z
-    sk = make_uint4(0u, 0u, d.z, 0u);
-    if ((uint32_t)lane < nb && ((d.y >> 16) & WF_ALIGNED))
-        sk = *(const EWT_GLOBAL uint4*)(uintptr_t)(((uint64_t)d.w << 32) | d.z);
+    // skip-index entry of an aligned window, loaded by every lane without a branch (lanes
+    // of dirty blocks and empty slots read a valid dummy and are masked at decode: a dirty
+    // block has no markers and its first word at position d.z).  No value of this batch is
+    // used before the next decode, so nothing here waits for memory.
+    const bool al = (uint32_t)lane < nb && ((d.y >> 16) & WF_ALIGNED);
+    alm = __ballot(al);
+    dz = d.z;
+    const uint64_t sa = al ? (((uint64_t)d.w << 32) | d.z) : (uint64_t)(uintptr_t)dummy;
+    sk = *(const EWT_GLOBAL uint4*)(uintptr_t)sa;
 #pragma unroll
     for (int g = 0; g < WIN_BATCH; ++g) {
         v[g] = 0;
@@ -805,20 +810,25 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                 // software pipeline: the loads of batch k + 1 are in flight while batch k
                 // is added into the planes
                 uint4 sk;
+                uint32_t dz;
+                uint64_t alm;
                 uint64_t v[WIN_BATCH];
                 uint32_t fl[WIN_BATCH];
-                issue_batch(win, wb, we, lane, sk, v, fl);
+                issue_batch(win, wb, we, lane, table, sk, dz, alm, v, fl);
                 for (uint32_t w0 = wb; w0 < we; w0 += (uint32_t)WIN_BATCH) {
                     // decode, branch-free over the batch: position of every word (span = L
                     // for a marker, 1 for a dirty word)
                     uint32_t r[WIN_BATCH];
                     uint64_t x[WIN_BATCH], fills[WIN_BATCH], lit[WIN_BATCH];
                     uint32_t any_fill = 0;
+                    // skip-index entries: aligned windows' loaded values, dirty blocks' defaults
+                    const uint32_t skx = lane_sel(alm, 0u, sk.x), sky = lane_sel(alm, 0u, sk.y);
+                    const uint32_t skz = lane_sel(alm, dz, sk.z);
 #pragma unroll
                     for (int g = 0; g < WIN_BATCH; ++g) {
-                        const uint32_t m0 = (uint32_t)__builtin_amdgcn_readlane((int)sk.x, g);
-                        const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)sk.y, g);
-                        const uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)sk.z, g);
+                        const uint32_t m0 = (uint32_t)__builtin_amdgcn_readlane((int)skx, g);
+                        const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)sky, g);
+                        const uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)skz, g);
                         const uint64_t M = ((uint64_t)m1 << 32) | m0;
                         const uint64_t inr = lane_range((fl[g] >> 1) & 63u, (fl[g] >> 7) & 127u);
                         x[g] = v[g];
@@ -841,8 +851,16 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                     }
                     // words in pruned groups add nothing
                     if (prune) {
+                        // branch-free: every lane reads a mask word (lanes outside the tile read
+                        // the last group's; lit already excludes them), all reads before one wait
+                        uint32_t mw[WIN_BATCH], gi[WIN_BATCH];
 #pragma unroll
-                        for (int g = 0; g < WIN_BATCH; ++g) lit[g] &= ~__ballot(pruned_at(pm, r[g] - tS));
+                        for (int g = 0; g < WIN_BATCH; ++g) {
+                            gi[g] = min((r[g] - tS) >> pm.sh, pm.ng - 1u);
+                            mw[g] = pm.w[gi[g] >> 5];
+                        }
+#pragma unroll
+                        for (int g = 0; g < WIN_BATCH; ++g) lit[g] &= ~__ballot((mw[g] >> (gi[g] & 31u)) & 1u);
                     }
                     // dirty words in range add at their tile-relative position
                     uint32_t act = 0;   // bit g: window g has a word to add
@@ -853,7 +871,8 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                         if (lit[g]) act |= 1u << g;
                     }
                     // next batch's loads
-                    if (w0 + (uint32_t)WIN_BATCH < we) issue_batch(win, w0 + (uint32_t)WIN_BATCH, we, lane, sk, v, fl);
+                    if (w0 + (uint32_t)WIN_BATCH < we)
+                        issue_batch(win, w0 + (uint32_t)WIN_BATCH, we, lane, table, sk, dz, alm, v, fl);
                     // ripple-carry adds, one plane at a time over the whole batch: all atomics
                     // of a plane are issued before any result is used, and the batch leaves
                     // once no lane carries (no per-window bookkeeping)
