@@ -161,9 +161,9 @@ struct Seg {
 __device__ __forceinline__ Seg locate(const BitmapDev& B, uint32_t t, uint32_t tS, uint32_t tE, uint32_t tiles) {
     Seg s;
     const bool has_next = t + 1 < tiles;
+    // both entries loaded without a branch (entry `tiles` is the end record, always present)
     const uint4 l0 = gp(B.loc)[t];
-    uint4 l1 = make_uint4(0u, 0u, 0u, 0u);
-    if (has_next) l1 = gp(B.loc)[t + 1];
+    const uint4 l1 = gp(B.loc)[t + 1];
     const uint32_t pm = l0.x, um = l0.y;
     const uint32_t f = l0.z & 1u, L = (l0.z >> 1) | (l0.w << 31), K = l0.w >> 1;
     const uint32_t fa = max(um, tS), fb = min(um + L, tE);
@@ -174,17 +174,14 @@ __device__ __forceinline__ Seg locate(const BitmapDev& B, uint32_t t, uint32_t t
     s.a_lit = pm + 1u + (la - (um + L));
     s.bs = pm + 1u + K;
     s.y0 = um + L + K;
-    s.be = s.bs;
-    if (has_next) {
-        if (l1.x != pm) {
-            const uint32_t L2 = (l1.z >> 1) | (l1.w << 31), K2 = l1.w >> 1;
-            const uint32_t lit_start = l1.y + L2;
-            const uint32_t inlit = tE > lit_start ? min(K2, tE - lit_start) : 0u;
-            s.be = l1.x + 1u + inlit;
-        }
-    } else if (s.bs < B.n_words) {
-        s.be = B.n_words;
-    }
+    // selects rather than branches, so that neither load is sunk into a branch and issued
+    // after an earlier wait
+    const uint32_t L2 = (l1.z >> 1) | (l1.w << 31), K2 = l1.w >> 1;
+    const uint32_t lit_start = l1.y + L2;
+    const uint32_t inlit = tE > lit_start ? min(K2, tE - lit_start) : 0u;
+    const uint32_t be_next = l1.x != pm ? l1.x + 1u + inlit : s.bs;
+    const uint32_t be_last = s.bs < B.n_words ? B.n_words : s.bs;
+    s.be = has_next ? be_next : be_last;
     s.onefull = f && fa == tS && fb == tE;
     s.zero = (s.fa >= s.fb) && s.cnt == 0 && s.be <= s.bs;
     return s;
@@ -612,10 +609,17 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             if (k < N) {
                 const BitmapDev B = input_of(q, table, k);
                 const uint4* src = (fine ? B.pres1 : B.pres) + (size_t)t * pv;
+                // every presence record and both locator entries are loaded before any is
+                // used (records past pv re-read the first one and are ignored), so the
+                // classify step waits for memory once
+                uint4 prv[PV_FINE];
+#pragma unroll
+                for (int v = 0; v < PV_FINE; ++v) prv[v] = gp(src)[(uint32_t)v < pv ? v : 0];
+                Seg s = locate(B, t, tS, tE, tiles);
 #pragma unroll
                 for (int v = 0; v < PV_FINE; ++v) {
                     if ((uint32_t)v < pv) {
-                        const uint4 pr = gp(src)[v];
+                        const uint4 pr = prv[v];
                         np += (uint32_t)(__popc(pr.x) + __popc(pr.y) + __popc(pr.z) + __popc(pr.w));
                         if (k < pcap) {
                             prs[(4 * v) * pcap + k] = pr.x;
@@ -625,7 +629,6 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                         }
                     }
                 }
-                Seg s = locate(B, t, tS, tE, tiles);
                 onefull = s.onefull;
                 nonzero = !s.zero;
                 if (kb == 0) { seg = s; B0 = B; }
