@@ -193,8 +193,10 @@ def bench_c4(args, E, torch):
     tuned = None if args.retune else A.lookup(f"{signature}_{sel_kind}")
     if tuned is None and (args.tune or args.retune):
         tuned = A.tune_batch(batch, step, f"{signature}_{sel_kind}", E.num_cus(), log=log)
+    if tuned:
+        A.apply(batch, tuned)
     grid = int(tuned["grid"]) if tuned else pb.grid
-    batch.set_grid(grid)
+    win_batch = int(tuned.get("win_batch", 7)) if tuned else 7
     total_in = pb.input_bytes
 
     for _ in range(args.warmup):
@@ -284,6 +286,7 @@ def bench_c4(args, E, torch):
         "config": {"workload": f"c4: {len(qs)} queries, pool {len(pool)} EWAH bitmaps, r=2^22, "
                                "d log-uniform [1e-4,0.3], N~U[2,256], T~U[1,N]",
                    "path": "batched persistent graph launch", "selector": sel_kind, "grid": grid,
+                   "win_batch": win_batch,
                    "input_bytes_per_step": total_in, "output_words_per_step": out_words},
         "bit_exact": bit_exact, "bit_exact_outputs_checked": checked,
         "selection_ms_per_plan": None if sel_ms is None else round(sel_ms, 4),
@@ -505,7 +508,10 @@ def bench_index(args, E, torch):
             tuned = None if args.retune else A.lookup(signature)
             if tuned is None and (args.tune or args.retune):
                 tuned = A.tune_batch(b, lambda: b.run(stream), signature, E.num_cus(), log=log)
-            b.set_grid(int(tuned["grid"]) if tuned else 2 * E.num_cus())   # two workgroups per CU
+            if tuned:
+                A.apply(b, tuned)
+            else:
+                b.set_grid(2 * E.num_cus())   # two workgroups per CU
             batches.append(b)
             groups.append({"kind": kind, "shape": sh, "queries": len(qd),
                            "input_bytes": int(sum(in_words[i] for i, _, _ in keep)) * 8, "qd": qd, "ix": ix,
@@ -529,7 +535,8 @@ def bench_index(args, E, torch):
         gms = events_time(lambda: b.run(stream), stream, max(3, args.steps))
         ow = int(g["out_n"][g["rows"]].sum().item())
         out_words += ow
-        per.append({"kind": g["kind"], "shape": g["shape"], "queries": g["queries"], "grid": b.grid, "ms": round(gms, 4),
+        per.append({"kind": g["kind"], "shape": g["shape"], "queries": g["queries"], "grid": b.grid,
+                    "win_batch": b.win_batch, "ms": round(gms, 4),
                     "GB/s": round(g["input_bytes"] / (gms / 1e3) / 1e9, 1), "out_words": ow})
         log(f"{g['kind']} {g['shape']}: {g['queries']} queries, {gms:.3f} ms, {per[-1]['GB/s']} GB/s")
     log(f"index workload: {ms:.3f} ms/step, {value:.1f} GB/s input")

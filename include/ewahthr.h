@@ -267,6 +267,11 @@ ewah_status ewah_batch_set_variants(ewah_batch* b, const uint32_t* variants);
 /* Sets the persistent grid size (workgroups); rebuilds the graph.  Synchronous. */
 ewah_status ewah_batch_set_grid(ewah_batch* b, uint32_t grid);
 
+/* Sets how many 64-word windows a wavefront decodes per batch of loads in the
+ * persistent kernel (4..7, default 7; a kernel is built for each), a knob of the
+ * autotuner; results never depend on it.  Rebuilds the graph.  Synchronous. */
+ewah_status ewah_batch_set_win_batch(ewah_batch* b, uint32_t win_batch);
+
 void ewah_batch_free(ewah_batch* b);
 
 /*

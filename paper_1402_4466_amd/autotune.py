@@ -1,6 +1,8 @@
-"""Autotuner of the batched launch: grid search over the persistent grid size
-for a planned batch, min of repeats, results cached in JSON keyed by GPU
-architecture, HIP runtime version and workload signature."""
+"""Autotuner of the batched launch: a search over the launch schedule of a planned
+batch -- the persistent grid (workgroups) and the windows a wavefront decodes per
+batch of loads (the persistent kernel is built for 4..7) -- min of repeated
+timed launches, results cached in JSON keyed by GPU architecture, HIP runtime
+version and workload signature.  Results never depend on the knobs."""
 from __future__ import annotations
 
 import json
@@ -8,6 +10,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "autotune_cache.json")
+WIN_BATCHES = (4, 5, 6, 7)
 
 
 def device_key() -> str:
@@ -29,32 +32,46 @@ def lookup(signature: str, path: str = CACHE):
     return load_cache(path).get(f"{device_key()}|{signature}")
 
 
-def tune_batch(batch, run_step, signature: str, n_cu: int, reps: int = 3, grids=None, path: str = CACHE,
-               log=None) -> dict:
-    """run_step() launches one full step on the current stream.  Tries each grid
-    size, keeps the fastest (min over reps), stores it in the cache."""
+def apply(batch, entry) -> None:
+    """Sets a cached schedule on a planned batch."""
+    batch.set_grid(int(entry["grid"]))
+    batch.set_win_batch(int(entry.get("win_batch", 7)))
+
+
+def _time(run_step, reps):
     import torch
-    grids = grids or sorted({n_cu // 2, (3 * n_cu) // 4, n_cu, (5 * n_cu) // 4, (3 * n_cu) // 2, 2 * n_cu})
-    res = {}
-    for g in grids:
-        batch.set_grid(g)
+    run_step()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
         run_step()
-        torch.cuda.synchronize()
-        best = float("inf")
-        for _ in range(reps):
-            s = torch.cuda.Event(enable_timing=True)
-            e = torch.cuda.Event(enable_timing=True)
-            s.record()
-            run_step()
-            e.record()
-            e.synchronize()
-            best = min(best, s.elapsed_time(e))
-        res[str(g)] = round(best, 4)
-        if log:
-            log(f"  grid {g}: {best:.3f} ms")
-    g_best = int(min(res, key=res.get))
-    batch.set_grid(g_best)
-    entry = {"grid": g_best, "ms": res}
+        e.record()
+        e.synchronize()
+        best = min(best, s.elapsed_time(e))
+    return best
+
+
+def tune_batch(batch, run_step, signature: str, n_cu: int, reps: int = 3, grids=None, win_batches=WIN_BATCHES,
+               path: str = CACHE, log=None) -> dict:
+    """run_step() launches one full step on the current stream.  Tries every (grid,
+    windows per batch) pair, keeps the fastest (min over reps), stores it in the cache."""
+    grids = grids or sorted({n_cu, (3 * n_cu) // 2, 2 * n_cu})
+    res = {}
+    for wb in win_batches:
+        batch.set_win_batch(wb)
+        for g in grids:
+            batch.set_grid(g)
+            ms = _time(run_step, reps)
+            res[f"{g}/{wb}"] = round(ms, 4)
+            if log:
+                log(f"  grid {g}, {wb} windows per batch: {ms:.3f} ms")
+    best = min(res, key=res.get)
+    g_best, wb_best = (int(x) for x in best.split("/"))
+    entry = {"grid": g_best, "win_batch": wb_best, "ms": res}
+    apply(batch, entry)
     cache = load_cache(path)
     cache[f"{device_key()}|{signature}"] = entry
     with open(path, "w") as f:

@@ -906,6 +906,7 @@ struct ewah_batch {
     uint64_t n_bits = 0;
     uint32_t nq = 0;
     uint32_t grid = 0;
+    int win_batch = 7;             // windows per wavefront batch of the persistent kernel (4..7)
     size_t smem = 0;
     int use_graph = 1;
     hipStream_t cap_stream = nullptr;
@@ -923,7 +924,7 @@ ewah_status batch_build_graph(ewah_batch* b) {
     HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = launch_bump(b->d_work, b->cap_stream);
     hipError_t e2 = launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1,
-                                 g.d_err, b->grid, b->smem, b->cap_stream);
+                                 g.d_err, b->grid, b->smem, b->cap_stream, nullptr, b->win_batch);
     hipError_t e3 = hipStreamEndCapture(b->cap_stream, &b->graph);
     HIPCHK(e1);
     HIPCHK(e2);
@@ -1040,7 +1041,7 @@ ewah_status ewah_batch_run(ewah_batch* b, void* hip_stream) {
     } else {
         HIPCHK(launch_bump(b->d_work, s));
         HIPCHK(launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1, g.d_err,
-                            b->grid, b->smem, s));
+                            b->grid, b->smem, s, nullptr, b->win_batch));
     }
     return EWAH_OK;
 }
@@ -1057,6 +1058,13 @@ ewah_status ewah_batch_set_grid(ewah_batch* b, uint32_t grid) {
     if (!b || grid == 0) return fail(EWAH_EINVAL, "bad argument");
     HIPCHK(hipDeviceSynchronize());
     b->grid = grid;
+    return batch_build_graph(b);
+}
+
+ewah_status ewah_batch_set_win_batch(ewah_batch* b, uint32_t win_batch) {
+    if (!b || win_batch < 4 || win_batch > 7) return fail(EWAH_EINVAL, "win_batch must be in 4..7");
+    HIPCHK(hipDeviceSynchronize());
+    b->win_batch = (int)win_batch;
     return batch_build_graph(b);
 }
 
@@ -1174,7 +1182,7 @@ ewah_status ewah_batch_time_queries(ewah_batch* b, uint32_t reps, float* busy_us
     for (uint32_t r = 0; r < reps; ++r) {
         HIPCHK(launch_bump(b->d_work, s));
         HIPCHK(launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1, g.d_err,
-                            b->grid, b->smem, s, b->d_itemt));
+                            b->grid, b->smem, s, b->d_itemt, b->win_batch));
         HIPCHK(hipMemcpyAsync(ticks.data(), b->d_itemt, (size_t)b->total * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         for (uint32_t q = 0; q < b->nq; ++q) {

@@ -244,7 +244,8 @@ hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* tic
                         hipStream_t s, uint32_t pred_kind = PRED_THRESHOLD);   // kind of *q.pd
 hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_t* tq, uint32_t nq, uint32_t total,
                         const BitmapDev* table, uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid,
-                        size_t smem, hipStream_t s, uint32_t* item_t = nullptr);   // item_t: per-item busy time
+                        size_t smem, hipStream_t s, uint32_t* item_t = nullptr,   // item_t: per-item busy time
+                        int win_batch = 7);   // windows per wavefront batch: 4..7
 hipError_t launch_bump(uint32_t* work, hipStream_t s);   // epoch at work[1], counters cleared
 hipError_t launch_zero_len(uint64_t* out_n, hipStream_t s);
 hipError_t set_smem_limits(size_t max_bytes);

@@ -340,8 +340,10 @@ __device__ Agg lookback(EWT_GLOBAL TileState* st, int t, uint32_t epoch, uint32_
 
 // ---------------------------------------------------------------- the tile
 
-// Cooperative windows taken by one wavefront at a time: all their loads are
-// issued before any of them is decoded.
+// Cooperative windows taken by one wavefront at a time (WB): all their loads are
+// issued before any of them is decoded.  Single queries take WIN_BATCH; the batched
+// kernel is built for WIN_BATCHES and the autotuner picks one per workload (more
+// windows in flight against the registers they hold).
 constexpr int WIN_BATCH = 7;
 
 #ifdef EWT_PHASE_TIMING
@@ -421,10 +423,11 @@ __device__ __forceinline__ uint4 window_entry(const uint64_t* words, const uint4
 // Reads the list entries of windows [w0, min(w0 + WIN_BATCH, we)) (lane g holds
 // entry g), fetches the skip-index entries of aligned windows (lane g) and
 // issues the data loads of all of them; empty slots read nothing and add nothing.
+template <int WB>
 __device__ __forceinline__ void issue_batch(const uint4* win, uint32_t w0, uint32_t we, int lane, const void* dummy,
-                                            uint4& sk, uint32_t& dz, uint64_t& alm, uint64_t (&v)[WIN_BATCH],
-                                            uint32_t (&fl)[WIN_BATCH]) {
-    const uint32_t nb = min((uint32_t)WIN_BATCH, we - w0);
+                                            uint4& sk, uint32_t& dz, uint64_t& alm, uint64_t (&v)[WB],
+                                            uint32_t (&fl)[WB]) {
+    const uint32_t nb = min((uint32_t)WB, we - w0);
     uint4 d = make_uint4(0u, 0u, 0u, 0u);
     if ((uint32_t)lane < nb) d = win[w0 + (uint32_t)lane];
     // skip-index entry of an aligned window, loaded by every lane without a branch (lanes
@@ -437,7 +440,7 @@ __device__ __forceinline__ void issue_batch(const uint4* win, uint32_t w0, uint3
     const uint64_t sa = al ? (((uint64_t)d.w << 32) | d.z) : (uint64_t)(uintptr_t)dummy;
     sk = *(const EWT_GLOBAL uint4*)(uintptr_t)sa;
 #pragma unroll
-    for (int g = 0; g < WIN_BATCH; ++g) {
+    for (int g = 0; g < WB; ++g) {
         v[g] = 0;
         fl[g] = 0;
         if ((uint32_t)g < nb) {
@@ -539,7 +542,8 @@ __device__ __forceinline__ BitmapDev input_of(const QueryDev& q, const BitmapDev
 
 static_assert((MAXN + 1u) * 4u <= (uint32_t)WCAP * 16u, "count histogram must fit in the window list");
 
-template <bool STAGED, bool GENERAL = false, bool MAXC = false, bool LOOPED = false, bool HIST = false>
+template <bool STAGED, bool GENERAL = false, bool MAXC = false, bool LOOPED = false, bool HIST = false,
+          int WB = WIN_BATCH>
 __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ table, uint32_t t,
                              uint32_t epoch, unsigned char* smem, uint32_t* err, uint32_t dbg_slot) {
     (void)dbg_slot;   // timestamp slot of debug builds
@@ -815,20 +819,20 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                 uint4 sk;
                 uint32_t dz;
                 uint64_t alm;
-                uint64_t v[WIN_BATCH];
-                uint32_t fl[WIN_BATCH];
+                uint64_t v[WB];
+                uint32_t fl[WB];
                 issue_batch(win, wb, we, lane, table, sk, dz, alm, v, fl);
-                for (uint32_t w0 = wb; w0 < we; w0 += (uint32_t)WIN_BATCH) {
+                for (uint32_t w0 = wb; w0 < we; w0 += (uint32_t)WB) {
                     // decode, branch-free over the batch: position of every word (span = L
                     // for a marker, 1 for a dirty word)
-                    uint32_t r[WIN_BATCH];
-                    uint64_t x[WIN_BATCH], fills[WIN_BATCH], lit[WIN_BATCH];
+                    uint32_t r[WB];
+                    uint64_t x[WB], fills[WB], lit[WB];
                     uint32_t any_fill = 0;
                     // skip-index entries: aligned windows' loaded values, dirty blocks' defaults
                     const uint32_t skx = lane_sel(alm, 0u, sk.x), sky = lane_sel(alm, 0u, sk.y);
                     const uint32_t skz = lane_sel(alm, dz, sk.z);
 #pragma unroll
-                    for (int g = 0; g < WIN_BATCH; ++g) {
+                    for (int g = 0; g < WB; ++g) {
                         const uint32_t m0 = (uint32_t)__builtin_amdgcn_readlane((int)skx, g);
                         const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)sky, g);
                         const uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)skz, g);
@@ -844,7 +848,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                     // one-fills of markers in range (rare): counted through the difference array
                     if (any_fill) {
 #pragma unroll
-                        for (int g = 0; g < WIN_BATCH; ++g) {
+                        for (int g = 0; g < WB; ++g) {
                             if (((any_fill >> g) & 1u) && ((fills[g] >> lane) & 1ull)) {
                                 const uint32_t L = (uint32_t)(x[g] >> 1);
                                 const uint32_t fa = max(r[g], tS), fb = min(r[g] + L, tE);
@@ -856,34 +860,34 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                     if (prune) {
                         // branch-free: every lane reads a mask word (lanes outside the tile read
                         // the last group's; lit already excludes them), all reads before one wait
-                        uint32_t mw[WIN_BATCH], gi[WIN_BATCH];
+                        uint32_t mw[WB], gi[WB];
 #pragma unroll
-                        for (int g = 0; g < WIN_BATCH; ++g) {
+                        for (int g = 0; g < WB; ++g) {
                             gi[g] = min((r[g] - tS) >> pm.sh, pm.ng - 1u);
                             mw[g] = pm.w[gi[g] >> 5];
                         }
 #pragma unroll
-                        for (int g = 0; g < WIN_BATCH; ++g) lit[g] &= ~__ballot((mw[g] >> (gi[g] & 31u)) & 1u);
+                        for (int g = 0; g < WB; ++g) lit[g] &= ~__ballot((mw[g] >> (gi[g] & 31u)) & 1u);
                     }
                     // dirty words in range add at their tile-relative position
                     uint32_t act = 0;   // bit g: window g has a word to add
 #pragma unroll
-                    for (int g = 0; g < WIN_BATCH; ++g) {
+                    for (int g = 0; g < WB; ++g) {
                         r[g] = lane_sel(lit[g], (uint32_t)lane, r[g] - tS);   // lanes without a word: distinct in-tile slots
                         x[g] = lane_sel64(lit[g], 0ull, x[g]);
                         if (lit[g]) act |= 1u << g;
                     }
                     // next batch's loads
-                    if (w0 + (uint32_t)WIN_BATCH < we)
-                        issue_batch(win, w0 + (uint32_t)WIN_BATCH, we, lane, table, sk, dz, alm, v, fl);
+                    if (w0 + (uint32_t)WB < we)
+                        issue_batch(win, w0 + (uint32_t)WB, we, lane, table, sk, dz, alm, v, fl);
                     // ripple-carry adds, one plane at a time over the whole batch: all atomics
                     // of a plane are issued before any result is used, and the batch leaves
                     // once no lane carries (no per-window bookkeeping)
                     if (act) {
                         for (int p = 0; p < PL; ++p) {
-                            uint64_t old[WIN_BATCH];
+                            uint64_t old[WB];
 #pragma unroll
-                            for (int g = 0; g < WIN_BATCH; ++g) {
+                            for (int g = 0; g < WB; ++g) {
                                 old[g] = plane_add<LOOPED>(planes, (uint32_t)p, r[g], x[g]);
                             }
                             // one wait for all of them (lgkmcnt(0)); without it the compiler cannot
@@ -891,7 +895,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                             __builtin_amdgcn_s_waitcnt(0xC07F);
                             uint64_t any = 0;
 #pragma unroll
-                            for (int g = 0; g < WIN_BATCH; ++g) {
+                            for (int g = 0; g < WB; ++g) {
                                 x[g] &= old[g];
                                 any |= x[g];
                             }
@@ -1419,6 +1423,7 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_max_kernel(QueryDev q, con
 // turn.  qtile[i] = first item of query i (qtile[nq] = total); tq[i] = query of item i.
 // item_t (null: off): per item, the wall-clock ticks its workgroup spent on it, the
 // measure of each query's cost inside a batch.
+template <int WB>
 __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
                                                           const uint32_t* __restrict__ tq, uint32_t nq,
                                                           const BitmapDev* __restrict__ table,
@@ -1450,8 +1455,9 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __r
         if (it >= total) break;
         const uint64_t t0 = item_t ? wall_clock64() : 0ull;
         QueryDev q = qs[qi];
-        if (use_looped(q.variant, q.N, q.T)) process_tile<true, false, false, true>(q, table, it - qtile[qi], epoch, smem, err, it);
-        else process_tile<true>(q, table, it - qtile[qi], epoch, smem, err, it);
+        if (use_looped(q.variant, q.N, q.T))
+            process_tile<true, false, false, true, false, WB>(q, table, it - qtile[qi], epoch, smem, err, it);
+        else process_tile<true, false, false, false, false, WB>(q, table, it - qtile[qi], epoch, smem, err, it);
         if (item_t && threadIdx.x == 0) item_t[it] = (uint32_t)(wall_clock64() - t0);
     }
 }
@@ -1502,12 +1508,19 @@ hipError_t set_smem_limits(size_t max_bytes) {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void*)thr_query_hist_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)thr_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
+    const void* batch_kernels[] = {(const void*)thr_batch_kernel<4>, (const void*)thr_batch_kernel<5>,
+                                   (const void*)thr_batch_kernel<6>, (const void*)thr_batch_kernel<7>};
+    for (const void* k : batch_kernels) {
+        e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 int batch_blocks_per_cu(size_t smem) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)thr_batch_kernel, BLOCK, smem) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)thr_batch_kernel<WIN_BATCH>, BLOCK, smem) != hipSuccess)
+        return 1;
     return n > 0 ? n : 1;
 }
 
@@ -1527,9 +1540,18 @@ hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* tic
 
 hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_t* tq, uint32_t nq, uint32_t total,
                         const BitmapDev* table, uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid,
-                        size_t smem, hipStream_t s, uint32_t* item_t) {
-    hipLaunchKernelGGL(thr_batch_kernel, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work, epoch_ptr, err,
-                       item_t);
+                        size_t smem, hipStream_t s, uint32_t* item_t, int win_batch) {
+    switch (win_batch) {
+        case 4: hipLaunchKernelGGL(thr_batch_kernel<4>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
+                                   epoch_ptr, err, item_t); break;
+        case 5: hipLaunchKernelGGL(thr_batch_kernel<5>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
+                                   epoch_ptr, err, item_t); break;
+        case 6: hipLaunchKernelGGL(thr_batch_kernel<6>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
+                                   epoch_ptr, err, item_t); break;
+        case 7: hipLaunchKernelGGL(thr_batch_kernel<7>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
+                                   epoch_ptr, err, item_t); break;
+        default: return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL(scan_batch_kernel, dim3(nq), dim3(SCAN_THREADS), 0, s, qs, epoch_ptr, err);
     hipLaunchKernelGGL(place_batch_kernel, dim3((total + 3) / 4), dim3(256), 0, s, qs, qtile, tq, total, epoch_ptr, err);
     return hipGetLastError();

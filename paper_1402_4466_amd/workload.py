@@ -35,10 +35,13 @@ class PooledBatch:
                              self.caps, [nbase + 8 * i for i in range(len(queries))], grid=E.num_cus(),
                              use_graph=use_graph)
         self.sel_kind = selector.apply(self.batch, stream) if selector is not None else "default"
+        self.tuned = None
         if grid is None:
-            tuned = A.lookup(f"{signature}_{self.sel_kind}") if signature else None
-            grid = int(tuned["grid"]) if tuned else 2 * E.num_cus()
+            self.tuned = A.lookup(f"{signature}_{self.sel_kind}") if signature else None
+            grid = int(self.tuned["grid"]) if self.tuned else 2 * E.num_cus()
         self.batch.set_grid(grid)
+        if self.tuned:
+            self.batch.set_win_batch(int(self.tuned.get("win_batch", 7)))
         self.grid = grid
         self.signature = signature
 

@@ -2,7 +2,8 @@
 MI355X).
 
 * T = 0 (every row), T = N + 1 and larger (no row) and N = 1 (the input itself) inside a
-  batch whose other queries do real work, on every counter variant, against the oracle;
+  batch whose other queries do real work, on every counter variant and every build of
+  the persistent kernel (4..7 windows per wavefront batch), against the oracle;
 * the planner sums (query, tile) items in 64 bits and rejects a batch of 2^31 or more
   items before it allocates anything (a 32-bit sum would wrap and size the tile states
   too small).
@@ -54,10 +55,11 @@ def test_batched_trivial_thresholds_and_single_inputs(G):
     wants = [O.threshold([pool[i] for i in idx], n_bits, T, want_hist=False)[0] for idx, T in qs]
     batch = E.Batch(bms, qs, [o.data_ptr() for o in outs], caps, [n.data_ptr() for n in ns], use_graph=True)
     try:
-        for v in codes:
+        for v, wb in [(c, w) for c in codes for w in (4, 5, 6, 7)]:
             batch.set_variants(np.full(len(qs), v, dtype=np.uint32))
+            batch.set_win_batch(wb)
             for rep in range(2):
-                _say(f"batched edges: variant {v:#x} replay {rep}")
+                _say(f"batched edges: variant {v:#x}, {wb} windows per batch, replay {rep}")
                 for o in outs:
                     o.fill_(-1)
                 batch.run()
