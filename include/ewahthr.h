@@ -182,8 +182,8 @@ ewah_status ewah_count_histogram(const ewah_bitmap* const* in, uint32_t n, uint6
  * As ewah_threshold, for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * call allocates nothing.  Its per-call device state (tile-order ticket, input
- * slots, one 64-byte tile state per tile) lives in a static device array of
- * about 272 KB that each GPU holds until the process ends; queries of more than
+ * slots, one 96-byte tile state per tile) lives in a static device array of
+ * about 400 KB that each GPU holds until the process ends; queries of more than
  * 4096 tiles (n_bits > 2^27) are EINVAL.  Every call on one GPU shares that
  * array: calls that overlap (on different streams) race, calls on one stream
  * are ordered.  The input slots go to the device by a pageable copy from a

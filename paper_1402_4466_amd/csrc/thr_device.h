@@ -106,6 +106,9 @@ struct TileState {
                           // 0..t-1, written by the placement scan
     uint64_t head[2];     // first two heads of the tile: position | local output index << 32;
                           // bits 16..17 of head[1]: number of heads, at most 2
+    uint64_t blk[3];      // single queries, tiles t = 64 k + 63 only: aggregate of the block of
+                          // tiles 64 k .. 64 k + 63 (look-back across blocks)
+    uint64_t pad;
 };
 
 // Output predicate of a query, a function f of the row count (a symmetric Boolean

@@ -272,30 +272,98 @@ __device__ __forceinline__ uint64_t lane_range(uint32_t lo, uint32_t hi) {
     return below_hi & (~0ull << lo);
 }
 
-// Exclusive prefix of the run-structure aggregate over tiles [0, t), by
-// decoupled look-back read 64 predecessors at a time: lane i looks at tile
-// base - i; the nearest tile that has published its inclusive prefix ends the
-// search, and the local aggregates of the tiles after it are reduced across
-// the wavefront (the aggregate is associative).  Called by one whole wavefront.
-__device__ Agg lookback(EWT_GLOBAL TileState* st, int t, uint32_t epoch, uint32_t* err) {
+// Reduces, in unit order, the aggregates held by the lanes of a wavefront: lane l holds
+// unit base - l (a tile or a block of 64 tiles, unit u starting at word u * unit_words);
+// `empty` lanes hold nothing and lie past the non-empty ones.  The result is broadcast.
+__device__ __forceinline__ Agg wave_reduce_back(Agg v, bool empty, int base, uint32_t unit_words) {
     const int lane = __lane_id();
-    bool acc_empty = true;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        Agg o;
+        o.n = __shfl_down(v.n, d, 64);
+        o.lh_pos = __shfl_down(v.lh_pos, d, 64);
+        o.lh_out = __shfl_down(v.lh_out, d, 64);
+        o.bits = __shfl_down(v.bits, d, 64);
+        const bool oe = __shfl_down((int)empty, d, 64) != 0 || lane + d >= 64;
+        if ((lane & (2 * d - 1)) == 0 && !oe) {
+            if (empty) { v = o; empty = false; }
+            else v = agg_combine(o, v, (uint32_t)(base - lane - d + 1) * unit_words);
+        }
+    }
+    Agg R;
+    R.n = __shfl(v.n, 0, 64);
+    R.lh_pos = __shfl(v.lh_pos, 0, 64);
+    R.lh_out = __shfl(v.lh_out, 0, 64);
+    R.bits = __shfl(v.bits, 0, 64);
+    return R;
+}
+
+// Exclusive prefix of the run-structure aggregate over tiles [0, t), by decoupled
+// look-back over two levels.  Round A reads the predecessors inside t's block of 64
+// tiles (lane l: tile t - 1 - l); the nearest one that has published its inclusive
+// prefix ends the search, the local aggregates of the tiles after it are reduced.  The
+// block's last tile reads all 63 locals instead and publishes the block's aggregate.
+// Round B then reads the earlier blocks, nearest first (lane l: block b - 1 - l, through
+// the state of its last tile): an inclusive prefix there ends the search, otherwise the
+// block aggregates are reduced.  A query of up to 4,096 tiles needs two rounds of loads,
+// where one per 64 predecessors was needed before.  Tiles are taken in ticket order, so a
+// tile only waits for states of tiles that started before it.  Called by one whole
+// wavefront; A is the tile's own aggregate (its words start at tS).
+__device__ Agg lookback(EWT_GLOBAL TileState* st, int t, const Agg& A, uint32_t tS, uint32_t epoch, uint32_t* err) {
+    const int lane = __lane_id();
+    const int p = t & 63, b = t >> 6;
     Agg acc;
     acc.n = 0; acc.lh_pos = 0; acc.lh_out = 0; acc.bits = 0;
-    int base = t - 1;
+    bool acc_empty = true;
     uint32_t spins = 0;
+    if (p > 0) {   // round A: the block's earlier tiles
+        const bool last = p == 63;   // reads every in-block local (no inclusive shortcut)
+        while (true) {
+            const int j = t - 1 - lane;
+            const bool inb = lane < p;
+            Agg vi, vl;
+            bool inc = false, loc = false;
+            if (inb) {
+                inc = agg_fetch(st[j].incl, epoch, vi);
+                loc = agg_fetch(st[j].local, epoch, vl);
+            }
+            const uint64_t incm = last ? 0ull : __ballot(inc);
+            const int linc = incm ? (__ffsll((long long)incm) - 1) : 64;
+            const bool need = inb && lane <= linc;
+            const bool ok = !need || (lane == linc ? inc : loc);
+            if (__ballot(!ok) != 0ull) {
+                if (++spins > (1u << 22)) {
+                    if (lane == 0) atomicOr(err, 1u);
+                    return acc;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                continue;
+            }
+            Agg v;
+            v.n = 0; v.lh_pos = 0; v.lh_out = 0; v.bits = 0;
+            if (need) v = (lane == linc) ? vi : vl;
+            acc = wave_reduce_back(v, !need, t - 1, (uint32_t)TW);
+            acc_empty = false;
+            if (last && lane == 0) agg_publish(st[t].blk, agg_combine(acc, A, tS), epoch);
+            if (linc < 64 || b == 0) return acc;   // an inclusive prefix, or block 0 read whole
+            break;
+        }
+    }
+    // round B: earlier blocks, nearest first
+    int bb = b - 1;
     while (true) {
-        const int j = base - lane;
-        Agg vi, vl;
-        bool inc = false, loc = false;
-        if (j >= 0) {
+        const int k = bb - lane;
+        const int j = 64 * k + 63;
+        Agg vi, vb;
+        bool inc = false, blk = false;
+        if (k >= 0) {
             inc = agg_fetch(st[j].incl, epoch, vi);
-            loc = agg_fetch(st[j].local, epoch, vl);
+            blk = agg_fetch(st[j].blk, epoch, vb);
         }
         const uint64_t incm = __ballot(inc);
         const int linc = incm ? (__ffsll((long long)incm) - 1) : 64;
-        const bool need = j >= 0 && lane <= linc;
-        const bool ok = !need || inc || loc;
+        const bool need = k >= 0 && lane <= linc;
+        const bool ok = !need || (lane == linc ? inc : blk);
         if (__ballot(!ok) != 0ull) {
             if (++spins > (1u << 22)) {
                 if (lane == 0) atomicOr(err, 1u);
@@ -306,35 +374,12 @@ __device__ Agg lookback(EWT_GLOBAL TileState* st, int t, uint32_t epoch, uint32_
         }
         Agg v;
         v.n = 0; v.lh_pos = 0; v.lh_out = 0; v.bits = 0;
-        if (need) v = (lane == linc) ? vi : vl;
-        bool empty = !need;
-        // tree reduction: lane i + d holds the lower (earlier) tiles
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            Agg o;
-            o.n = __shfl_down(v.n, d, 64);
-            o.lh_pos = __shfl_down(v.lh_pos, d, 64);
-            o.lh_out = __shfl_down(v.lh_out, d, 64);
-            o.bits = __shfl_down(v.bits, d, 64);
-            const bool oe = __shfl_down((int)empty, d, 64) != 0 || lane + d >= 64;
-            if ((lane & (2 * d - 1)) == 0 && !oe) {
-                if (empty) { v = o; empty = false; }
-                else v = agg_combine(o, v, (uint32_t)(base - lane - d + 1) * (uint32_t)TW);
-            }
-        }
-        Agg R;
-        R.n = __shfl(v.n, 0, 64);
-        R.lh_pos = __shfl(v.lh_pos, 0, 64);
-        R.lh_out = __shfl(v.lh_out, 0, 64);
-        R.bits = __shfl(v.bits, 0, 64);
-        acc = acc_empty ? R : agg_combine(R, acc, (uint32_t)(base + 1) * (uint32_t)TW);
+        if (need) v = (lane == linc) ? vi : vb;
+        const Agg R = wave_reduce_back(v, !need, bb, 64u * (uint32_t)TW);
+        acc = acc_empty ? R : agg_combine(R, acc, (uint32_t)(bb + 1) * 64u * (uint32_t)TW);
         acc_empty = false;
-        if (linc < 64) return acc;
-        base -= 64;
-        if (base < 0) {   // tile 0 always publishes an inclusive value: cannot get here
-            if (lane == 0) atomicOr(err, 2u);
-            return acc;
-        }
+        if (linc < 64 || bb - 64 < 0) return acc;   // an inclusive prefix, or every block read
+        bb -= 64;
     }
 }
 
@@ -743,20 +788,54 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     // read after the last barrier, the same for every wavefront, and the exit is taken
     // here, outside every loop that holds a barrier, so all wavefronts leave together.
     // An all-ones tile holding the last, partial word is excluded: that word is a literal.
-    if constexpr (STAGED && !GENERAL && !MAXC && !HIST) {
+    // Single threshold queries take the same exit: wavefront 0 publishes the aggregate,
+    // looks back and writes the at most two marker words such a tile owns (closing the run
+    // left open before it unless its fill continues that run; the last tile's marker).
+    if constexpr (!GENERAL && !MAXC && !HIST) {
         const uint32_t umode = (uint32_t)__builtin_amdgcn_readfirstlane((int)mode);
         if (umode == 2u || (umode == 1u && !(tE == U && q.tail_bits))) {
-            if (tid == 0) {
-                const uint32_t c = umode == 1u ? 1u : 0u;
-                Agg A;
-                A.n = 1;
-                A.lh_pos = tS;
-                A.lh_out = 0;
-                A.bits = c | (c << 2) | (1u << 4) | (c << 5);
-                EWT_GLOBAL TileState* st = gp(q.state);
-                st[t].head[0] = 0ull;
-                st[t].head[1] = 1ull << 16;
-                agg_publish(st[t].local, A, epoch);
+            const uint32_t c = umode == 1u ? 1u : 0u;
+            Agg A;
+            A.n = 1;
+            A.lh_pos = tS;
+            A.lh_out = 0;
+            A.bits = c | (c << 2) | (1u << 4) | (c << 5);
+            EWT_GLOBAL TileState* st = gp(q.state);
+            if constexpr (STAGED) {
+                if (tid == 0) {
+                    st[t].head[0] = 0ull;
+                    st[t].head[1] = 1ull << 16;
+                    agg_publish(st[t].local, A, epoch);
+                }
+            } else if (wave == 0) {
+                if (lane == 0) agg_publish(st[t].local, A, epoch);
+                Agg X;
+                X.n = 0; X.lh_pos = 0; X.lh_out = 0; X.bits = 3u << 2;
+                Agg I = A;
+                if (t > 0) {
+                    X = lookback(st, (int)t, A, tS, epoch, err);
+                    I = agg_combine(X, A, tS);
+                }
+                if (lane == 0) {
+                    agg_publish(st[t].incl, I, epoch);
+                    const uint64_t cap = q.cap;
+                    EWT_GLOBAL uint64_t* out = gp(q.out);
+                    const bool merge = t > 0 && ((X.bits >> 2) & 3u) == c;
+                    if (t > 0 && !merge) {   // this tile's head closes the run left open before it
+                        const uint32_t K = X.n - X.lh_out - 1u;
+                        const uint32_t L = (tS - X.lh_pos) - K;
+                        if (X.lh_out < cap) out[X.lh_out] = ((X.bits >> 5) & 1u) | ((uint64_t)L << 1) | ((uint64_t)K << 33);
+                    }
+                    if (t == tiles - 1) {    // the last tile closes the last run
+                        const uint32_t lpos = merge ? X.lh_pos : tS;
+                        const uint32_t lout = merge ? X.lh_out : X.n;
+                        const uint64_t lf = merge ? ((X.bits >> 5) & 1u) : c;
+                        const uint32_t K = I.n - lout - 1u;
+                        const uint32_t L = (U - lpos) - K;
+                        if (lout < cap) out[lout] = lf | ((uint64_t)L << 1) | ((uint64_t)K << 33);
+                        *gp(q.out_n) = I.n;
+                    }
+                }
             }
             return;
         }
@@ -1136,9 +1215,9 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             Agg X;
             X.n = 0; X.lh_pos = 0; X.lh_out = 0; X.bits = 3u << 2;
             Agg I = A;
+            if (lane == 0) agg_publish(st[t].local, A, epoch);   // tile 0's too: a block's last tile reads it
             if (t > 0) {
-                if (lane == 0) agg_publish(st[t].local, A, epoch);
-                X = lookback(st, (int)t, epoch, err);
+                X = lookback(st, (int)t, A, tS, epoch, err);
                 I = agg_combine(X, A, tS);
             }
             if (lane == 0) {
