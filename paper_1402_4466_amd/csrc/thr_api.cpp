@@ -110,7 +110,7 @@ static __device__ __align__(256) unsigned char scratch[NA_BYTES];
 static uint32_t na_host_slots[MAXN + 1];   // host staging of the input slots (static: no allocation)
 
 // Clears n 64-bit words (used instead of hipMemsetAsync so that the call stays capturable).
-__global__ void na_clear_kernel(uint64_t* p, size_t n) {
+__global__ void clear_words_kernel(uint64_t* p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
@@ -621,6 +621,20 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
     q.variant = variant ? variant
                         : ((!pred && T_eff >= 1u && T_eff <= 2u) ? var_make(false, 8, 8, true) : ewah_default_variant());
     q.pd = pred ? (const PredDev*)(c->d_ids + pred_off) : nullptr;
+    if (!batched && !pred && n <= IDS_INLINE) {
+        // the slots travel in the kernel arguments: nothing to upload, nothing to wait for
+        InlineIds iv;
+        for (uint32_t i = 0; i < n; ++i) iv.v[i] = in[i]->slot;
+        q.ids = nullptr;
+        if ((++c->epoch & 0xFFFFu) == 0) {   // 16-bit tags wrapped: clear stale states
+            hipLaunchKernelGGL(clear_words_kernel, dim3(256), dim3(256), 0, s, (uint64_t*)c->d_state,
+                               c->state_cap * sizeof(TileState) / 8);
+            HIPCHK(hipGetLastError());
+            c->epoch = 1;
+        }
+        HIPCHK(launch_query(q, g.d_table, c->d_ticket, c->epoch, g.d_err, s, PRED_THRESHOLD, &iv));
+        return EWAH_OK;
+    }
     HIPCHK(hipEventSynchronize(c->ev));   // previous upload from the staging buffer is done
     for (uint32_t i = 0; i < n; ++i) c->h_ids[i] = in[i]->slot;
     if (pred) {
@@ -650,7 +664,9 @@ ewah_status run_plain(const ewah_bitmap* const* in, uint32_t n, uint32_t T, cons
         return EWAH_OK;
     }
     if ((++c->epoch & 0xFFFFu) == 0) {   // 16-bit tags wrapped: clear stale states
-        HIPCHK(hipMemsetAsync(c->d_state, 0, c->state_cap * sizeof(TileState), s));
+        hipLaunchKernelGGL(clear_words_kernel, dim3(256), dim3(256), 0, s, (uint64_t*)c->d_state,
+                           c->state_cap * sizeof(TileState) / 8);
+        HIPCHK(hipGetLastError());
         c->epoch = 1;
     }
     HIPCHK(launch_query(q, g.d_table, c->d_ticket, c->epoch, g.d_err, s, pred ? pred->kind : (uint32_t)PRED_THRESHOLD));
@@ -790,17 +806,23 @@ ewah_status ewah_threshold_noalloc(const ewah_bitmap* const* in, uint32_t n, uin
     TileState* d_state = (TileState*)(g.na_ptr + NA_STATE_OFF);
     // tile states carry a 16-bit launch tag; on a wrap the stale states are cleared
     if ((++g.na_epoch & 0xFFFFu) == 0) {
-        hipLaunchKernelGGL(na_clear_kernel, dim3(256), dim3(256), 0, s, (uint64_t*)d_state,
+        hipLaunchKernelGGL(clear_words_kernel, dim3(256), dim3(256), 0, s, (uint64_t*)d_state,
                            (size_t)NA_MAX_TILES * sizeof(TileState) / 8);
         HIPCHK(hipGetLastError());
         g.na_epoch = 1;
     }
-    // input slots: a pageable copy, staged by the runtime before the call returns, so the
-    // static host buffer is free for the next call
-    for (uint32_t i = 0; i < n; ++i) na_host_slots[i] = in[i]->slot;
-    HIPCHK(hipMemcpyAsync(d_slots, na_host_slots, (size_t)n * 4, hipMemcpyHostToDevice, s));
+    // input slots: in the kernel arguments for up to IDS_INLINE inputs, else a pageable
+    // copy, staged by the runtime before the call returns, so the static host buffer is
+    // free for the next call
+    InlineIds iv;
+    if (n <= IDS_INLINE) {
+        for (uint32_t i = 0; i < n; ++i) iv.v[i] = in[i]->slot;
+    } else {
+        for (uint32_t i = 0; i < n; ++i) na_host_slots[i] = in[i]->slot;
+        HIPCHK(hipMemcpyAsync(d_slots, na_host_slots, (size_t)n * 4, hipMemcpyHostToDevice, s));
+    }
     QueryDev q{};
-    q.ids = d_slots;
+    q.ids = n <= IDS_INLINE ? nullptr : d_slots;
     q.out = out_words_dev;
     q.out_n = out_n_words_dev;
     q.state = d_state;
@@ -814,7 +836,7 @@ ewah_status ewah_threshold_noalloc(const ewah_bitmap* const* in, uint32_t n, uin
     q.variant = (T >= 1u && T <= 2u) ? var_make(false, 8, 8, true) : ewah_default_variant();
     q.pd = nullptr;
     q.bms = nullptr;
-    HIPCHK(launch_query(q, g.d_table, d_ticket, g.na_epoch, g.d_err, s, PRED_THRESHOLD));
+    HIPCHK(launch_query(q, g.d_table, d_ticket, g.na_epoch, g.d_err, s, PRED_THRESHOLD, &iv));
     return EWAH_OK;
 }
 

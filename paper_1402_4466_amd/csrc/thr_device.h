@@ -242,9 +242,18 @@ __host__ __device__ inline size_t tile_smem_bytes(uint32_t N) {
     return b;
 }
 
-// Host-side launchers (defined with the kernels).
+// Slots of a threshold query of at most IDS_INLINE inputs travel in the kernel
+// arguments (no upload before the launch); the kernel reads them where q.ids is null.
+constexpr uint32_t IDS_INLINE = 256;
+struct InlineIds {
+    uint32_t v[IDS_INLINE];
+};
+
+// Host-side launchers (defined with the kernels).  ids: the slots when q.ids is null
+// (threshold queries of at most IDS_INLINE inputs only).
 hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* ticket, uint32_t epoch, uint32_t* err,
-                        hipStream_t s, uint32_t pred_kind = PRED_THRESHOLD);   // kind of *q.pd
+                        hipStream_t s, uint32_t pred_kind = PRED_THRESHOLD,   // kind of *q.pd
+                        const InlineIds* ids = nullptr);
 hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_t* tq, uint32_t nq, uint32_t total,
                         const BitmapDev* table, uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid,
                         size_t smem, hipStream_t s, uint32_t* item_t = nullptr,   // item_t: per-item busy time

@@ -809,6 +809,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                 }
             } else if (wave == 0) {
                 if (lane == 0) agg_publish(st[t].local, A, epoch);
+                EWT_PHASE(6);
                 Agg X;
                 X.n = 0; X.lh_pos = 0; X.lh_out = 0; X.bits = 3u << 2;
                 Agg I = A;
@@ -836,6 +837,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                         *gp(q.out_n) = I.n;
                     }
                 }
+                EWT_PHASE(7);
             }
             return;
         }
@@ -1425,7 +1427,8 @@ __device__ void place_tile(const QueryDev& q, uint32_t t, uint32_t epoch, uint32
 // One query, one workgroup per tile.  Tiles are taken in ticket order so that a
 // tile only ever waits for tiles that are already running or done.
 __global__ __launch_bounds__(BLOCK, 4) void thr_query_kernel(QueryDev q, const BitmapDev* __restrict__ table,
-                                                          uint32_t* ticket, uint32_t epoch, uint32_t* err) {
+                                                          uint32_t* ticket, uint32_t epoch, uint32_t* err,
+                                                          InlineIds ids) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_t;
     if (threadIdx.x == 0) {
@@ -1434,12 +1437,15 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_kernel(QueryDev q, const B
         s_t = t;
     }
     __syncthreads();
-    process_tile<false>(q, table, s_t, epoch, smem, err, s_t);
+    QueryDev qq = q;
+    if (!qq.ids) qq.ids = ids.v;   // slots in the kernel arguments
+    process_tile<false>(qq, table, s_t, epoch, smem, err, s_t);
 }
 
 // The same with the unary per-row counter (use_looped(q.variant, q.N, q.T) holds).
 __global__ __launch_bounds__(BLOCK, 4) void thr_query_looped_kernel(QueryDev q, const BitmapDev* __restrict__ table,
-                                                                 uint32_t* ticket, uint32_t epoch, uint32_t* err) {
+                                                                 uint32_t* ticket, uint32_t epoch, uint32_t* err,
+                                                                 InlineIds ids) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_t;
     if (threadIdx.x == 0) {
@@ -1448,7 +1454,9 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_looped_kernel(QueryDev q, 
         s_t = t;
     }
     __syncthreads();
-    process_tile<false, false, false, true>(q, table, s_t, epoch, smem, err, s_t);
+    QueryDev qq = q;
+    if (!qq.ids) qq.ids = ids.v;   // slots in the kernel arguments
+    process_tile<false, false, false, true>(qq, table, s_t, epoch, smem, err, s_t);
 }
 
 // The same for a general symmetric predicate (q.pd: intervals of counts or parity),
@@ -1604,11 +1612,15 @@ int batch_blocks_per_cu(size_t smem) {
 }
 
 hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* ticket, uint32_t epoch, uint32_t* err,
-                        hipStream_t s, uint32_t pred_kind) {
+                        hipStream_t s, uint32_t pred_kind, const InlineIds* ids) {
     size_t smem = tile_smem_bytes(q.N);
+    if (!q.ids && (q.pd || !ids || q.N > IDS_INLINE)) return hipErrorInvalidValue;
+    static const InlineIds none{};
+    const InlineIds& iv = ids ? *ids : none;
     if (!q.pd && use_looped(q.variant, q.N, q.T))
-        hipLaunchKernelGGL(thr_query_looped_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
-    else if (!q.pd) hipLaunchKernelGGL(thr_query_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
+        hipLaunchKernelGGL(thr_query_looped_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err, iv);
+    else if (!q.pd)
+        hipLaunchKernelGGL(thr_query_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err, iv);
     else if (pred_kind == PRED_HIST)
         hipLaunchKernelGGL(thr_query_hist_kernel, dim3(q.tiles), dim3(BLOCK), smem, s, q, table, ticket, epoch, err);
     else if (pred_kind == PRED_MAXCOUNT)

@@ -300,6 +300,29 @@ def test_single_query_around_the_switch(G):
                label=f"{tiles} tiles")
 
 
+def test_slots_inline_and_uploaded(G):
+    """Threshold queries of up to 256 inputs pass their slots in the kernel arguments, wider
+    ones upload them: 255, 256 and 257 inputs, through the allocating and the allocation-free
+    entry points, with the same inputs in reversed order (the slots differ, the result not)."""
+    E = G.lib()
+    n_bits = 3 * TW_ROWS + 129
+    streams = D.bitmaps(D.MARKOV, 64.0, 30000.0, n_bits, [D.key(8830, k) for k in range(257)])
+    bms = G.register(streams, n_bits)
+    try:
+        for n in (255, 256, 257):
+            for T in (1, 2, 4):
+                want, _ = O.threshold(streams[:n], n_bits, T, want_hist=False)
+                assert np.array_equal(G.gpu_threshold(bms[:n], T), want), (n, T)
+                assert np.array_equal(G.gpu_threshold(bms[:n][::-1], T), want), (n, T, "reversed")
+                out, out_n, cap = G.alloc_out(n_bits, sum(len(s) for s in streams[:n]))
+                E.threshold_noalloc(bms[:n], T, out.data_ptr(), cap, out_n.data_ptr())
+                assert np.array_equal(G.fetch(out, out_n), want), (n, T, "noalloc")
+        assert E.device_errors() == 0
+    finally:
+        for b in bms:
+            b.release()
+
+
 def _bits_to_stream(bits):
     """Row i = character / element i (the walk-throughs list rows left to right)."""
     w = 0
