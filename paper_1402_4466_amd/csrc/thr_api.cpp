@@ -125,7 +125,7 @@ struct Built {
     std::vector<uint4> loc;    // per tile boundary: covering marker index, its run start, the marker word
     std::vector<uint4> desc;   // per CHUNK words: marker mask (lo, hi), position of the chunk's first word
     std::vector<uint4> pres;   // per tile PV_COARSE records: 4-word groups holding a dirty word or a one-fill
-    std::vector<uint4> pres1;  // per tile PV_FINE records: words that are dirty or inside a one-fill
+    std::vector<uint32_t> presq;   // per tile PQ_WORDS words: quarter-word groups holding a one, their count
     ewah_stats st{};
 };
 
@@ -149,6 +149,7 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
     const uint64_t nchunks = (nw + CHUNK - 1) / CHUNK;
     b.loc.assign(tiles + 1, make_uint4(0, 0, 0, 0));
     std::vector<uint64_t> gbits((tiles * TW + 63) / 64 + 1, 0);   // words holding a dirty word or a one-fill
+    std::vector<uint64_t> qbits(tiles * TW * 4 / 64 + 1, 0);       // quarter words holding a one
     b.desc.assign(nchunks, make_uint4(0, 0, 0, 0));
     const uint64_t tailmask = (n_bits % 64) ? ((1ull << (n_bits % 64)) - 1) : ~0ull;
     ewah_stats& st = b.st;
@@ -178,7 +179,10 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
         if (bit < 32) b.desc[c].x |= 1u << bit;
         else b.desc[c].y |= 1u << (bit - 32);
         if (p % CHUNK == 0) b.desc[c].z = (uint32_t)u;
-        if (f && L) set_bits(gbits, u, u + L - 1);
+        if (f && L) {
+            set_bits(gbits, u, u + L - 1);
+            set_bits(qbits, 4 * u, 4 * (u + L) - 1);
+        }
         if (K) set_bits(gbits, u + L, u + L + K - 1);
         if (L + K > 0) {
             const uint4 e = make_uint4((uint32_t)p, (uint32_t)u, (uint32_t)m, (uint32_t)(m >> 32));
@@ -204,6 +208,8 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
             uint64_t v = w[q];
             const uint64_t nbits = (pos == U - 1) ? (n_bits - (U - 1) * 64) : 64;
             if (pos == U - 1) v &= tailmask;
+            for (uint64_t j = 0; j < 4; ++j)
+                if ((v >> (16 * j)) & 0xFFFFull) qbits[(4 * pos + j) / 64] |= 1ull << ((4 * pos + j) % 64);
             st.popcount += popc64(v);
             run_bits(v, nbits);
         }
@@ -213,28 +219,33 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
     }
     if (u != U) return fail(EWAH_EFORMAT, "stream covers " + std::to_string(u) + " words, expected " + std::to_string(U));
     if (tiles) b.loc[tiles] = make_uint4((uint32_t)nw, (uint32_t)U, 0, 0);
-    // per tile: the word bits as they are, and their OR over each group of 4 words
-    b.pres1.assign(tiles * PV_FINE, make_uint4(0, 0, 0, 0));
+    // per tile: the quarter bits and their count, and the word bits ORed over each group of 4 words
+    b.presq.assign(tiles * PQ_WORDS, 0u);
     b.pres.assign(tiles * PV_COARSE, make_uint4(0, 0, 0, 0));
     static_assert(TW % 64 == 0 && GW_COARSE == 4, "presence record packing");
     for (uint64_t t = 0; t < tiles; ++t) {
+        const uint64_t* qw = qbits.data() + t * (NQ_TILE / 64);
+        uint32_t* rec = b.presq.data() + t * PQ_WORDS;
+        uint32_t nq = 0;
+        for (int k = 0; k < NQ_TILE / 64; ++k) {
+            rec[2 * k] = (uint32_t)qw[k];
+            rec[2 * k + 1] = (uint32_t)(qw[k] >> 32);
+            nq += (uint32_t)popc64(qw[k]);
+        }
+        rec[NQ_TILE / 32] = nq;
         const uint64_t* w = gbits.data() + t * (TW / 64);
-        uint32_t f[4 * PV_FINE] = {}, c[4 * PV_COARSE] = {};
+        uint32_t c[4 * PV_COARSE] = {};
         for (int k = 0; k < TW / 64; ++k) {
-            f[2 * k] = (uint32_t)w[k];
-            f[2 * k + 1] = (uint32_t)(w[k] >> 32);
             uint64_t y = w[k] | (w[k] >> 1);
             y |= y >> 2;   // bit 4i: OR of bits 4i .. 4i + 3
             uint32_t q = 0;
             for (int i = 0; i < 16; ++i) q |= (uint32_t)((y >> (4 * i)) & 1u) << i;
             c[k / 2] |= q << (16 * (k % 2));
         }
-        for (int v = 0; v < PV_FINE; ++v)
-            b.pres1[t * PV_FINE + v] = make_uint4(f[4 * v], f[4 * v + 1], f[4 * v + 2], f[4 * v + 3]);
         for (int v = 0; v < PV_COARSE; ++v)
             b.pres[t * PV_COARSE + v] = make_uint4(c[4 * v], c[4 * v + 1], c[4 * v + 2], c[4 * v + 3]);
     }
-    st.index_bytes = (b.loc.size() + b.desc.size() + b.pres.size() + b.pres1.size()) * sizeof(uint4);
+    st.index_bytes = (b.loc.size() + b.desc.size() + b.pres.size()) * sizeof(uint4) + b.presq.size() * 4;
     return EWAH_OK;
 }
 
@@ -443,10 +454,10 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
         if (bad < count) return fail(bad_st, "bitmap " + std::to_string(bad) + ": " + bad_msg);
     }
     // one device arena per call; per bitmap [words padded to CHUNK, plus CHUNK zero words |
-    // skip index | locator | 4-word-group presence | word presence], each part 256-byte aligned.  The image is assembled on the host
+    // skip index | locator | 4-word-group presence | quarter-word presence], each part 256-byte aligned.  The image is assembled on the host
     // and uploaded in pieces of at most kStage bytes.
     constexpr size_t kStage = 256ull << 20;
-    struct Layout { size_t words, desc, loc, pres, pres1, end; };
+    struct Layout { size_t words, desc, loc, pres, presq, end; };
     std::vector<Layout> lay(count);
     size_t total = 0;
     for (uint32_t i = 0; i < count; ++i) {
@@ -456,8 +467,8 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
         l.desc = l.words + align256((nch * CHUNK + CHUNK) * 8);
         l.loc = l.desc + align256(nch * 16);
         l.pres = l.loc + align256(built[i].loc.size() * 16);
-        l.pres1 = l.pres + align256(std::max<size_t>(built[i].pres.size(), 1) * 16);
-        l.end = l.pres1 + align256(std::max<size_t>(built[i].pres1.size(), 1) * 16);
+        l.presq = l.pres + align256(std::max<size_t>(built[i].pres.size(), 1) * 16);
+        l.end = l.presq + align256(std::max<size_t>(built[i].presq.size(), 1) * 4);
         total = l.end;
     }
     Arena* arena = new Arena();
@@ -484,8 +495,8 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
             std::memcpy(stage.data() + (lay[i].loc - base), built[i].loc.data(), built[i].loc.size() * 16);
             if (!built[i].pres.empty())
                 std::memcpy(stage.data() + (lay[i].pres - base), built[i].pres.data(), built[i].pres.size() * 16);
-            if (!built[i].pres1.empty())
-                std::memcpy(stage.data() + (lay[i].pres1 - base), built[i].pres1.data(), built[i].pres1.size() * 16);
+            if (!built[i].presq.empty())
+                std::memcpy(stage.data() + (lay[i].presq - base), built[i].presq.data(), built[i].presq.size() * 4);
         }
         HIPCHK(hipMemcpy((char*)arena->d + base, stage.data(), len, hipMemcpyHostToDevice));
         i0 = i1;
@@ -497,7 +508,7 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
         b->dev.loc = (const uint4*)(base + lay[i].loc);
         b->dev.desc = (const uint4*)(base + lay[i].desc);
         b->dev.pres = (const uint4*)(base + lay[i].pres);
-        b->dev.pres1 = (const uint4*)(base + lay[i].pres1);
+        b->dev.presq = (const uint32_t*)(base + lay[i].presq);
         b->dev.n_words = (uint32_t)v[i].n_words;
         b->dev.U = (uint32_t)((v[i].n_bits + 63) / 64);
         b->stats = built[i].st;

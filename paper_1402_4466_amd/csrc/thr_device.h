@@ -56,15 +56,18 @@ namespace ewt {
 constexpr int TW = EWT_TILE_WORDS;    // tile width in uncompressed 64-bit words (= locator granularity)
 constexpr int BLOCK = EWT_TILE_WORDS; // threads per workgroup (one per word position of a tile)
 constexpr int NWAVES = BLOCK / 64;
-// Presence records (upper bounds on row counts): which groups of words of a tile an
-// input touches.  Two granularities are kept: single words, used by queries of up to
-// PCAP_FINE inputs, and groups of 4 words, used by wider queries.
+// Presence records (upper bounds on row counts): which groups of rows of a tile an
+// input can hold a one in.  Two granularities are kept: quarters of a word (16 rows),
+// used by queries of up to PCAP_FINE inputs, and groups of 4 words, used by wider
+// queries.  Either way the tile routine prunes whole words (NG_FINE groups of one word).
 constexpr int GW_COARSE = 4;
 constexpr int NG_FINE = TW;                   // groups per tile, single words
 constexpr int NG_COARSE = TW / GW_COARSE;     // groups per tile, 4-word groups
 constexpr int PV_FINE = NG_FINE / 128;        // 16-byte records per tile and bitmap
 constexpr int PV_COARSE = NG_COARSE / 128;
 constexpr int PMW_MAX = NG_FINE / 32;         // 32-bit words of the largest group mask
+constexpr int NQ_TILE = 4 * TW;               // quarter-word groups per tile
+constexpr int PQ_WORDS = NQ_TILE / 32 + 4;    // 32-bit words per tile and bitmap: the bits, their count, pad
 static_assert(TW % 512 == 0 && NG_FINE <= BLOCK, "presence groups per tile");
 constexpr int CHUNK = 64;         // compressed words per skip-index entry (one wavefront)
 constexpr int MAXP = 12;          // bit planes: inputs per query < 2^12 (LDS budget)
@@ -82,8 +85,10 @@ struct BitmapDev {
     uint32_t U;              // uncompressed words
     const uint4* pres;       // per tile PV_COARSE records: bit g set iff words [4g, 4g + 4) of the
                              // tile hold a dirty word or a one-fill (the input can contribute there)
-    const uint4* pres1;      // per tile PV_FINE records: bit w set iff word w of the tile is a dirty
-                             // word or lies in a one-fill
+    const uint32_t* presq;   // per tile PQ_WORDS words: in words 0 .. NQ_TILE / 32 - 1, bit 4w + j set
+                             // iff rows [16j, 16j + 16) of word w of the tile hold a one (a one-fill,
+                             // or a nonzero quarter of a dirty word); word NQ_TILE / 32: how many
+                             // such quarters the tile has
 };
 
 // Associative run-structure aggregate of a range of output words (see encode step).

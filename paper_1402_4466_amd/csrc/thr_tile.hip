@@ -570,11 +570,113 @@ __device__ __forceinline__ void count_quads(const uint32_t* prs, uint32_t pcap, 
     }
 }
 
+// Quarter-word bounds of a tile of a query of at most PCAP_FINE inputs.  qptr[k]: the
+// tile's quarter record of input k (LDS).  Wavefront w adds the records of inputs w,
+// w + 8, ... (lane l holds quarters 32l .. 32l + 31), eight at a time through a
+// carry-save-adder tree into a bit-sliced counter of QP planes; the eight counters are
+// summed through LDS (part: 7 * QP * 64 words) in three rounds; wavefront 0 compares
+// the sums with tz and writes the word mask (bit w: all four quarters of word w are
+// touched by fewer than tz inputs, w < nPos) as bytes to pmw.  All threads must call.
+constexpr int QP = 9;
+
+__device__ __forceinline__ void csa(uint32_t& h, uint32_t& l, uint32_t a, uint32_t b, uint32_t c) {
+    const uint32_t u = a ^ b;
+    h = (a & b) | (u & c);
+    l = u ^ c;
+}
+
+__device__ __forceinline__ void quarter_bounds(const uint32_t* const* qptr, uint32_t N, uint32_t tz, uint32_t nPos,
+                                               uint32_t* part, uint32_t* pmw) {
+    const int lane = __lane_id();
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t ni = N > wave ? (N - wave + 7u) / 8u : 0u;   // inputs of this wavefront (at most 32)
+    uint32_t x[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) x[i] = 0u;
+    // every record word is loaded before any is added
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+        if ((uint32_t)i < ni) x[i] = gp(qptr[wave + 8u * (uint32_t)i])[lane];
+    uint32_t c[QP];
+#pragma unroll
+    for (int p = 0; p < QP; ++p) c[p] = 0u;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        if ((uint32_t)(8 * g) >= ni) break;
+        const uint32_t* y = x + 8 * g;
+        uint32_t h1, l1, h2, l2, h3, l3, g1, m1;
+        csa(h1, l1, y[0], y[1], y[2]);
+        csa(h2, l2, l1, y[3], y[4]);
+        csa(h3, l3, l2, y[5], y[6]);
+        const uint32_t o = l3 ^ y[7], h4 = l3 & y[7];
+        csa(g1, m1, h1, h2, h3);
+        const uint32_t tw = m1 ^ h4, g2 = m1 & h4;
+        const uint32_t f = g1 ^ g2, e = g1 & g2;
+        // counter += o + 2 tw + 4 f + 8 e
+        uint32_t cy = c[0] & o;
+        c[0] ^= o;
+        uint32_t u;
+        u = c[1] ^ tw; { const uint32_t n = (c[1] & tw) | (u & cy); c[1] = u ^ cy; cy = n; }
+        u = c[2] ^ f;  { const uint32_t n = (c[2] & f) | (u & cy); c[2] = u ^ cy; cy = n; }
+        u = c[3] ^ e;  { const uint32_t n = (c[3] & e) | (u & cy); c[3] = u ^ cy; cy = n; }
+#pragma unroll
+        for (int p = 4; p < QP; ++p) {
+            const uint32_t n = c[p] & cy;
+            c[p] ^= cy;
+            cy = n;
+        }
+    }
+    // wavefronts w + s add into w (s = 4, 2, 1), each round in its own part of the scratch
+    uint32_t off = 0;
+#pragma unroll
+    for (uint32_t sft = 4; sft >= 1; sft >>= 1) {
+        if (wave >= sft && wave < 2 * sft) {
+#pragma unroll
+            for (int p = 0; p < QP; ++p) part[off + ((wave - sft) * QP + (uint32_t)p) * 64u + (uint32_t)lane] = c[p];
+        }
+        __syncthreads();
+        if (wave < sft) {
+            uint32_t cy = 0;
+#pragma unroll
+            for (int p = 0; p < QP; ++p) {
+                const uint32_t b = part[off + (wave * QP + (uint32_t)p) * 64u + (uint32_t)lane];
+                const uint32_t u = c[p] ^ b;
+                const uint32_t n = (c[p] & b) | (u & cy);
+                c[p] = u ^ cy;
+                cy = n;
+            }
+        }
+        off += sft * QP * 64u;
+    }
+    if (wave == 0) {
+        // quarters below tz, most significant plane first
+        uint32_t gt = 0u, eq = ~0u;
+#pragma unroll
+        for (int p = QP - 1; p >= 0; --p) {
+            const uint32_t tb = ((tz >> p) & 1u) ? ~0u : 0u;
+            gt |= eq & c[p] & ~tb;
+            eq &= ~(c[p] ^ tb);
+        }
+        const uint32_t lt = (tz >> QP) ? ~0u : ~(gt | eq);
+        uint32_t m = lt & (lt >> 1);
+        m &= m >> 2;   // bit 4i: all four quarters of word 8 lane + i
+        uint32_t w8 = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w8 |= ((m >> (4 * i)) & 1u) << i;
+        const uint32_t w0 = 8u * (uint32_t)lane;
+        const uint32_t nv = nPos > w0 ? min(nPos - w0, 8u) : 0u;
+        w8 &= (1u << nv) - 1u;
+        ((unsigned char*)pmw)[lane] = (unsigned char)w8;
+    }
+}
+
 // Staged inputs per granularity (the window list holds 16 * WCAP bytes).
 constexpr uint32_t PCAP_FINE = (uint32_t)(WCAP / PV_FINE);
 constexpr uint32_t PCAP_COARSE = (uint32_t)(WCAP / PV_COARSE);
 static_assert((NG_FINE / 4) * 4 == BLOCK && (NG_COARSE / 4) * 16 == BLOCK, "lanes per quad of groups");
 static_assert(PCAP_FINE / 4 < 256u && PCAP_COARSE / 16 < 256u, "byte counters");
+static_assert(PCAP_FINE < (1u << QP) && PCAP_FINE <= 8u * 32u, "quarter counts fit QP planes, 32 inputs per wavefront");
+static_assert(7 * QP * 64 * 4 <= WCAP * 16, "quarter count scratch fits the window list");
 
 // STAGED: the tile writes its words to the staging area and publishes its
 // aggregate (a placement pass finishes the output); otherwise it finds the prefix
@@ -618,6 +720,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     // dense-row list the per-group counts
     uint32_t* prs = (uint32_t*)win;
     uint32_t* gcnt = (uint32_t*)dense;
+    const uint32_t** qptr = (const uint32_t**)dense;   // quarter records of the inputs (fine presence)
     if (tid < 8) misc[tid] = 0;
     if (tid < PMW_MAX) misc[M_PR + tid] = 0;
     // largest count: one read of the running maximum for the whole workgroup (other
@@ -647,9 +750,10 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     const bool fine = N <= PCAP_FINE;
     const uint32_t gsh = fine ? 0u : 2u;   // log2 of the words per group
     const uint32_t ng = fine ? (uint32_t)NG_FINE : (uint32_t)NG_COARSE;
-    const uint32_t pv = fine ? (uint32_t)PV_FINE : (uint32_t)PV_COARSE;
     const uint32_t pcap = fine ? PCAP_FINE : PCAP_COARSE;
     const uint32_t ngv = (nPos + (1u << gsh) - 1u) >> gsh;   // groups inside the tile
+    // presence groups an input touching all of the tile has: quarters, or 4-word groups
+    const uint32_t nfull = fine ? 4u * nPos : ngv;
     if (!trivial) {
         for (uint32_t kb = 0; kb < N; kb += BLOCK) {
             uint32_t k = kb + (uint32_t)tid;
@@ -657,25 +761,26 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             uint32_t np = 0;
             if (k < N) {
                 const BitmapDev B = input_of(q, table, k);
-                const uint4* src = (fine ? B.pres1 : B.pres) + (size_t)t * pv;
-                // every presence record and both locator entries are loaded before any is
-                // used (records past pv re-read the first one and are ignored), so the
-                // classify step waits for memory once
-                uint4 prv[PV_FINE];
-#pragma unroll
-                for (int v = 0; v < PV_FINE; ++v) prv[v] = gp(src)[(uint32_t)v < pv ? v : 0];
+                // the presence count or record and both locator entries are loaded before
+                // any is used, so the classify step waits for memory once
+                const uint32_t* qr = B.presq + (size_t)t * PQ_WORDS;
+                uint4 pr = make_uint4(0u, 0u, 0u, 0u);
+                uint32_t qc = 0;
+                static_assert(PV_COARSE == 1, "one 4-word-group record per tile");
+                if (fine) qc = gp(qr)[NQ_TILE / 32];
+                else pr = gp(B.pres)[t];
                 Seg s = locate(B, t, tS, tE, tiles);
-#pragma unroll
-                for (int v = 0; v < PV_FINE; ++v) {
-                    if ((uint32_t)v < pv) {
-                        const uint4 pr = prv[v];
-                        np += (uint32_t)(__popc(pr.x) + __popc(pr.y) + __popc(pr.z) + __popc(pr.w));
-                        if (k < pcap) {
-                            prs[(4 * v) * pcap + k] = pr.x;
-                            prs[(4 * v + 1) * pcap + k] = pr.y;
-                            prs[(4 * v + 2) * pcap + k] = pr.z;
-                            prs[(4 * v + 3) * pcap + k] = pr.w;
-                        }
+                if (fine) {
+                    // quarter counts; the records are read by the bounds step
+                    np = qc;
+                    qptr[k] = qr;
+                } else {
+                    np = (uint32_t)(__popc(pr.x) + __popc(pr.y) + __popc(pr.z) + __popc(pr.w));
+                    if (k < pcap) {
+                        prs[k] = pr.x;
+                        prs[pcap + k] = pr.y;
+                        prs[2 * pcap + k] = pr.z;
+                        prs[3 * pcap + k] = pr.w;
                     }
                 }
                 onefull = s.onefull;
@@ -684,7 +789,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             }
             // one LDS atomic per wavefront and counter
             const uint32_t c1 = (uint32_t)__popcll(__ballot(onefull)), c2 = (uint32_t)__popcll(__ballot(nonzero));
-            const uint32_t c3 = (uint32_t)__popcll(__ballot(np == ngv && k < N));
+            const uint32_t c3 = (uint32_t)__popcll(__ballot(np == nfull && k < N));
             const uint32_t c4 = wave_incl_scan(np);
             if (lane == 63) {
                 if (c1) atomicAdd(&misc[M_ONEFULL], c1);
@@ -749,8 +854,8 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     const uint32_t gate = (q.variant >> VAR_GATE_SHIFT) & 3u;
     const uint64_t gnum = gate == GATE_1_5 ? 15ull : 11ull;
     if (mode == 0 && misc[M_DFULL] < Tz && gate != GATE_NEVER &&
-        (gate == GATE_ALWAYS || 10ull * Tz * ngv > gnum * misc[M_PSUM])) {
-        if (fine) count_quads<4>(prs, PCAP_FINE, min(N, PCAP_FINE), gcnt);
+        (gate == GATE_ALWAYS || 10ull * Tz * nfull > gnum * misc[M_PSUM])) {
+        if (fine) quarter_bounds(qptr, N, Tz, nPos, prs, misc + M_PR);
         else count_quads<16>(prs, PCAP_COARSE, min(N, PCAP_COARSE), gcnt);
         if (N > pcap) {   // the rest of very wide queries (4-word groups): wavefront ballots
             __syncthreads();
@@ -768,7 +873,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             }
         }
         __syncthreads();
-        if ((uint32_t)tid < ng) {
+        if (!fine && (uint32_t)tid < ng) {
             const uint64_t m = __ballot(gcnt[tid] < Tz && (uint32_t)tid < ngv);
             if ((tid & 63) == 0) { misc[M_PR + 2 * (tid >> 6)] = (uint32_t)m; misc[M_PR + 2 * (tid >> 6) + 1] = (uint32_t)(m >> 32); }
         }
