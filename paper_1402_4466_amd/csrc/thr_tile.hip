@@ -912,6 +912,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                     st[t].head[1] = 1ull << 16;
                     agg_publish(st[t].local, A, epoch);
                 }
+                EWT_PHASE(7);
             } else if (wave == 0) {
                 if (lane == 0) agg_publish(st[t].local, A, epoch);
                 EWT_PHASE(6);
