@@ -1029,7 +1029,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                         const uint32_t span = lane_sel(M, 1u, (uint32_t)(x[g] >> 1));
                         r[g] = p0 + wave_incl_scan_dpp(span) - span;
                         fills[g] = __ballot((uint32_t)x[g] & 1u) & M & inr;
-                        lit[g] = ~M & inr & __ballot(r[g] >= tS) & __ballot(r[g] < tE);
+                        lit[g] = ~M & inr & __ballot(r[g] - tS < nPos);
                         any_fill |= fills[g] ? (1u << g) : 0u;
                     }
                     // one-fills of markers in range (rare): counted through the difference array
@@ -1046,11 +1046,11 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                     // words in pruned groups add nothing
                     if (prune) {
                         // branch-free: every lane reads a mask word (lanes outside the tile read
-                        // the last group's; lit already excludes them), all reads before one wait
+                        // some group's; lit already excludes them), all reads before one wait
                         uint32_t mw[WB], gi[WB];
 #pragma unroll
                         for (int g = 0; g < WB; ++g) {
-                            gi[g] = min((r[g] - tS) >> pm.sh, pm.ng - 1u);
+                            gi[g] = ((r[g] - tS) & (uint32_t)(TW - 1)) >> pm.sh;
                             mw[g] = pm.w[gi[g] >> 5];
                         }
 #pragma unroll
@@ -1060,7 +1060,9 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                     uint32_t act = 0;   // bit g: window g has a word to add
 #pragma unroll
                     for (int g = 0; g < WB; ++g) {
-                        r[g] = lane_sel(lit[g], (uint32_t)lane, r[g] - tS);   // lanes without a word: distinct in-tile slots
+                        // lanes without a word (x = 0) add nothing; their slot keeps the window's
+                        // lane-to-position stride, so the 64 lanes fall on distinct LDS banks
+                        r[g] = (r[g] - tS) & (uint32_t)(TW - 1);
                         x[g] = lane_sel64(lit[g], 0ull, x[g]);
                         if (lit[g]) act |= 1u << g;
                     }
