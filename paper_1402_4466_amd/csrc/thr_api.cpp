@@ -125,7 +125,8 @@ struct Built {
     std::vector<uint4> loc;    // per tile boundary: covering marker index, its run start, the marker word
     std::vector<uint4> desc;   // per CHUNK words: marker mask (lo, hi), position of the chunk's first word
     std::vector<uint4> pres;   // per tile PV_COARSE records: 4-word groups holding a dirty word or a one-fill
-    std::vector<uint32_t> presq;   // per tile PQ_WORDS words: quarter-word groups holding a one, their count
+    std::vector<uint32_t> presq;   // per tile PQ_WORDS words: quarter-word groups holding a one, their count,
+                                   // 8-row groups holding a one
     ewah_stats st{};
 };
 
@@ -150,6 +151,7 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
     b.loc.assign(tiles + 1, make_uint4(0, 0, 0, 0));
     std::vector<uint64_t> gbits((tiles * TW + 63) / 64 + 1, 0);   // words holding a dirty word or a one-fill
     std::vector<uint64_t> qbits(tiles * TW * 4 / 64 + 1, 0);       // quarter words holding a one
+    std::vector<uint64_t> obits(tiles * TW * 8 / 64 + 1, 0);       // 8-row groups holding a one
     b.desc.assign(nchunks, make_uint4(0, 0, 0, 0));
     const uint64_t tailmask = (n_bits % 64) ? ((1ull << (n_bits % 64)) - 1) : ~0ull;
     ewah_stats& st = b.st;
@@ -182,6 +184,7 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
         if (f && L) {
             set_bits(gbits, u, u + L - 1);
             set_bits(qbits, 4 * u, 4 * (u + L) - 1);
+            set_bits(obits, 8 * u, 8 * (u + L) - 1);
         }
         if (K) set_bits(gbits, u + L, u + L + K - 1);
         if (L + K > 0) {
@@ -210,6 +213,8 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
             if (pos == U - 1) v &= tailmask;
             for (uint64_t j = 0; j < 4; ++j)
                 if ((v >> (16 * j)) & 0xFFFFull) qbits[(4 * pos + j) / 64] |= 1ull << ((4 * pos + j) % 64);
+            for (uint64_t j = 0; j < 8; ++j)
+                if ((v >> (8 * j)) & 0xFFull) obits[(8 * pos + j) / 64] |= 1ull << ((8 * pos + j) % 64);
             st.popcount += popc64(v);
             run_bits(v, nbits);
         }
@@ -233,6 +238,11 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
             nq += (uint32_t)popc64(qw[k]);
         }
         rec[NQ_TILE / 32] = nq;
+        const uint64_t* ow = obits.data() + t * (NO_TILE / 64);
+        for (int k = 0; k < NO_TILE / 64; ++k) {
+            rec[PQ_OCT + 2 * k] = (uint32_t)ow[k];
+            rec[PQ_OCT + 2 * k + 1] = (uint32_t)(ow[k] >> 32);
+        }
         const uint64_t* w = gbits.data() + t * (TW / 64);
         uint32_t c[4 * PV_COARSE] = {};
         for (int k = 0; k < TW / 64; ++k) {

@@ -67,7 +67,9 @@ constexpr int PV_FINE = NG_FINE / 128;        // 16-byte records per tile and bi
 constexpr int PV_COARSE = NG_COARSE / 128;
 constexpr int PMW_MAX = NG_FINE / 32;         // 32-bit words of the largest group mask
 constexpr int NQ_TILE = 4 * TW;               // quarter-word groups per tile
-constexpr int PQ_WORDS = NQ_TILE / 32 + 4;    // 32-bit words per tile and bitmap: the bits, their count, pad
+constexpr int NO_TILE = 8 * TW;               // 8-row groups per tile
+constexpr int PQ_OCT = NQ_TILE / 32 + 4;      // record word where the 8-row bits start
+constexpr int PQ_WORDS = PQ_OCT + NO_TILE / 32;   // 32-bit words per tile and bitmap
 static_assert(TW % 512 == 0 && NG_FINE <= BLOCK, "presence groups per tile");
 constexpr int CHUNK = 64;         // compressed words per skip-index entry (one wavefront)
 constexpr int MAXP = 12;          // bit planes: inputs per query < 2^12 (LDS budget)
@@ -88,7 +90,8 @@ struct BitmapDev {
     const uint32_t* presq;   // per tile PQ_WORDS words: in words 0 .. NQ_TILE / 32 - 1, bit 4w + j set
                              // iff rows [16j, 16j + 16) of word w of the tile hold a one (a one-fill,
                              // or a nonzero quarter of a dirty word); word NQ_TILE / 32: how many
-                             // such quarters the tile has
+                             // such quarters the tile has; from word PQ_OCT, bit 8w + j set iff
+                             // rows [8j, 8j + 8) of word w hold a one
 };
 
 // Associative run-structure aggregate of a range of output words (see encode step).

@@ -570,13 +570,13 @@ __device__ __forceinline__ void count_quads(const uint32_t* prs, uint32_t pcap, 
     }
 }
 
-// Quarter-word bounds of a tile of a query of at most PCAP_FINE inputs.  qptr[k]: the
-// tile's quarter record of input k (LDS).  Wavefront w adds the records of inputs w,
-// w + 8, ... (lane l holds quarters 32l .. 32l + 31), eight at a time through a
-// carry-save-adder tree into a bit-sliced counter of QP planes; the eight counters are
-// summed through LDS (part: 7 * QP * 64 words) in three rounds; wavefront 0 compares
-// the sums with tz and writes the word mask (bit w: all four quarters of word w are
-// touched by fewer than tz inputs, w < nPos) as bytes to pmw.  All threads must call.
+// Per-group bounds of a tile of a query of at most PCAP_FINE inputs, from its presence
+// records (qptr[k]: the tile's record of input k, in LDS).  One pass: lane l of wavefront w
+// adds record word off + l of inputs w, w + 8, ... (32 groups; lanes with skip set read
+// nothing and add zeros), eight records at a time through a carry-save-adder tree, into a
+// bit-sliced counter of QP planes; the eight wavefronts' counters are summed through LDS
+// (part: 7 * QP * 64 words) in three rounds, and wavefront 0 gets the groups whose sum is
+// below tz.  All threads must call.
 constexpr int QP = 9;
 
 __device__ __forceinline__ void csa(uint32_t& h, uint32_t& l, uint32_t a, uint32_t b, uint32_t c) {
@@ -585,8 +585,8 @@ __device__ __forceinline__ void csa(uint32_t& h, uint32_t& l, uint32_t a, uint32
     l = u ^ c;
 }
 
-__device__ __forceinline__ void quarter_bounds(const uint32_t* const* qptr, uint32_t N, uint32_t tz, uint32_t nPos,
-                                               uint32_t* part, uint32_t* pmw) {
+__device__ __forceinline__ uint32_t bound_pass(const uint32_t* const* qptr, uint32_t N, uint32_t off, bool skip,
+                                               uint32_t tz, uint32_t* part) {
     const int lane = __lane_id();
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t ni = N > wave ? (N - wave + 7u) / 8u : 0u;   // inputs of this wavefront (at most 32)
@@ -596,7 +596,7 @@ __device__ __forceinline__ void quarter_bounds(const uint32_t* const* qptr, uint
     // every record word is loaded before any is added
 #pragma unroll
     for (int i = 0; i < 32; ++i)
-        if ((uint32_t)i < ni) x[i] = gp(qptr[wave + 8u * (uint32_t)i])[lane];
+        if ((uint32_t)i < ni && !skip) x[i] = gp(qptr[wave + 8u * (uint32_t)i])[off];
     uint32_t c[QP];
 #pragma unroll
     for (int p = 0; p < QP; ++p) c[p] = 0u;
@@ -627,47 +627,83 @@ __device__ __forceinline__ void quarter_bounds(const uint32_t* const* qptr, uint
         }
     }
     // wavefronts w + s add into w (s = 4, 2, 1), each round in its own part of the scratch
-    uint32_t off = 0;
+    uint32_t po = 0;
 #pragma unroll
     for (uint32_t sft = 4; sft >= 1; sft >>= 1) {
         if (wave >= sft && wave < 2 * sft) {
 #pragma unroll
-            for (int p = 0; p < QP; ++p) part[off + ((wave - sft) * QP + (uint32_t)p) * 64u + (uint32_t)lane] = c[p];
+            for (int p = 0; p < QP; ++p) part[po + ((wave - sft) * QP + (uint32_t)p) * 64u + (uint32_t)lane] = c[p];
         }
         __syncthreads();
         if (wave < sft) {
             uint32_t cy = 0;
 #pragma unroll
             for (int p = 0; p < QP; ++p) {
-                const uint32_t b = part[off + (wave * QP + (uint32_t)p) * 64u + (uint32_t)lane];
+                const uint32_t b = part[po + (wave * QP + (uint32_t)p) * 64u + (uint32_t)lane];
                 const uint32_t u = c[p] ^ b;
                 const uint32_t n = (c[p] & b) | (u & cy);
                 c[p] = u ^ cy;
                 cy = n;
             }
         }
-        off += sft * QP * 64u;
+        po += sft * QP * 64u;
     }
-    if (wave == 0) {
-        // quarters below tz, most significant plane first
-        uint32_t gt = 0u, eq = ~0u;
+    // groups below tz, most significant plane first (wavefront 0 holds the sums)
+    uint32_t gt = 0u, eq = ~0u;
 #pragma unroll
-        for (int p = QP - 1; p >= 0; --p) {
-            const uint32_t tb = ((tz >> p) & 1u) ? ~0u : 0u;
-            gt |= eq & c[p] & ~tb;
-            eq &= ~(c[p] ^ tb);
+    for (int p = QP - 1; p >= 0; --p) {
+        const uint32_t tb = ((tz >> p) & 1u) ? ~0u : 0u;
+        gt |= eq & c[p] & ~tb;
+        eq &= ~(c[p] ^ tb);
+    }
+    return (tz >> QP) ? ~0u : ~(gt | eq);
+}
+
+// Word mask of a tile of a query of at most PCAP_FINE inputs, as bytes at pmw (byte l: words
+// 8l .. 8l + 7, bit set: every row count of the word is below tz; words past nPos clear).
+// First from the quarter records (16 rows per group); if that leaves words of the tile in
+// play, the words still in play are bounded again from the 8-row records, which settles most
+// of the tiles the quarters leave almost settled.  All threads must call.
+__device__ __forceinline__ void fine_bounds(const uint32_t* const* qptr, uint32_t N, uint32_t tz, uint32_t nPos,
+                                            uint32_t* part, uint32_t* pmw, uint32_t* flag) {
+    const int lane = __lane_id();
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t w0 = 8u * (uint32_t)lane;
+    const uint32_t vmask = (1u << (nPos > w0 ? min(nPos - w0, 8u) : 0u)) - 1u;   // words of this lane in the tile
+    // pass 0: quarters (lane l holds quarters 32l .. 32l + 31, four per word); passes 1 and 2:
+    // the 8-row groups of words w0 + 4h .. w0 + 4h + 3 (h = pass - 1), record word PQ_OCT + 2l + h,
+    // where some of those words are still in play
+    uint32_t w8 = 0;
+#pragma unroll 1
+    for (uint32_t pass = 0; pass < 3; ++pass) {
+        const uint32_t h = pass > 0 ? pass - 1u : 0u;
+        const bool skip = pass > 0 && ((w8 | ~vmask) >> (4 * h) & 15u) == 15u;
+        const uint32_t off = pass == 0 ? (uint32_t)lane : (uint32_t)PQ_OCT + 2u * (uint32_t)lane + h;
+        const uint32_t lt = bound_pass(qptr, N, off, skip, tz, part);
+        if (pass == 0) {
+            uint32_t m = lt & (lt >> 1);
+            m &= m >> 2;   // bit 4i: all four quarters of word w0 + i
+#pragma unroll
+            for (int i = 0; i < 8; ++i) w8 |= ((m >> (4 * i)) & 1u) << i;
+            w8 &= vmask;
+            // the words every lane's passes 1 and 2 start from (wavefront 0 holds the sums)
+            if (wave == 0) {
+                ((unsigned char*)pmw)[lane] = (unsigned char)w8;
+                const bool open = __ballot(w8 != vmask) != 0ull;
+                if (lane == 0) *flag = open ? 1u : 0u;
+            }
+            __syncthreads();
+            if (*flag == 0u) return;   // nothing left in play (uniform: read from LDS after a barrier)
+            w8 = ((const unsigned char*)pmw)[lane];
+        } else {
+            uint32_t m = lt & (lt >> 1);
+            m &= m >> 2;
+            m &= m >> 4;   // bit 8i: all eight 8-row groups of word w0 + 4h + i
+#pragma unroll
+            for (int i = 0; i < 4; ++i) w8 |= ((m >> (8 * i)) & 1u) << (4 * h + (uint32_t)i);
         }
-        const uint32_t lt = (tz >> QP) ? ~0u : ~(gt | eq);
-        uint32_t m = lt & (lt >> 1);
-        m &= m >> 2;   // bit 4i: all four quarters of word 8 lane + i
-        uint32_t w8 = 0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) w8 |= ((m >> (4 * i)) & 1u) << i;
-        const uint32_t w0 = 8u * (uint32_t)lane;
-        const uint32_t nv = nPos > w0 ? min(nPos - w0, 8u) : 0u;
-        w8 &= (1u << nv) - 1u;
-        ((unsigned char*)pmw)[lane] = (unsigned char)w8;
     }
+    if (wave == 0) ((unsigned char*)pmw)[lane] = (unsigned char)(w8 & vmask);
 }
 
 // Staged inputs per granularity (the window list holds 16 * WCAP bytes).
@@ -855,7 +891,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     const uint64_t gnum = gate == GATE_1_5 ? 15ull : 11ull;
     if (mode == 0 && misc[M_DFULL] < Tz && gate != GATE_NEVER &&
         (gate == GATE_ALWAYS || 10ull * Tz * nfull > gnum * misc[M_PSUM])) {
-        if (fine) quarter_bounds(qptr, N, Tz, nPos, prs, misc + M_PR);
+        if (fine) fine_bounds(qptr, N, Tz, nPos, prs, misc + M_PR, misc + M_TMP);
         else count_quads<16>(prs, PCAP_COARSE, min(N, PCAP_COARSE), gcnt);
         if (N > pcap) {   // the rest of very wide queries (4-word groups): wavefront ballots
             __syncthreads();
