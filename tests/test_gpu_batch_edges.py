@@ -6,7 +6,9 @@ MI355X).
   the persistent kernel (4..7 windows per wavefront batch), against the oracle;
 * the planner sums (query, tile) items in 64 bits and rejects a batch of 2^31 or more
   items before it allocates anything (a 32-bit sum would wrap and size the tile states
-  too small).
+  too small);
+* inputs built so that the quarter-word bounds leave every word in play and the 8-row
+  bounds settle whole tiles, with a hot spot where neither may prune.
 """
 import sys
 
@@ -93,6 +95,63 @@ def test_batch_plan_rejects_item_overflow(G):
                     [out_n.data_ptr() + 8 * i for i in range(nq)], use_graph=False)
         assert e.value.code == E.EINVAL and "too many tiles" in str(e.value), str(e.value)
         assert E.device_errors() == 0
+    finally:
+        for b in bms:
+            b.release()
+
+
+def test_eight_row_bounds_settle_what_quarters_cannot(G):
+    """Inputs 0-1 hold ones only in rows 0-7 of every word, inputs 2-3 only in rows 8-15: at
+    T = 3 each word's first quarter is touched by four inputs (the quarter bounds prune nothing)
+    but each 8-row group by two (the 8-row bounds settle the tile). Input 4 adds rows 0-7 of
+    some words of the second tile (counts reach 3 there: those words must not be pruned), and
+    input 5 a few rows 48-63. Single queries and batches, every gate, against the oracle."""
+    import torch
+    E = G.lib()
+    TWW = 512
+    U = 3 * TWW + 5                             # three tiles and a ragged one
+    n_bits = U * 64 - 17
+    rng = np.random.default_rng(8080)
+    def words(mask_fn):
+        w = np.zeros(U, dtype=np.uint64)
+        for i in range(U):
+            w[i] = np.uint64(mask_fn(i))
+        if n_bits % 64:
+            w[-1] &= np.uint64((1 << (n_bits % 64)) - 1)
+        return w
+    lo = lambda: int(rng.integers(1, 256))
+    dense = [words(lambda i: lo()), words(lambda i: lo()),
+             words(lambda i: lo() << 8), words(lambda i: lo() << 8),
+             words(lambda i: lo() if TWW + 100 <= i < TWW + 140 else 0),
+             words(lambda i: (lo() << 48) if i % 97 == 0 else 0)]
+    streams = [O.encode(d, n_bits) for d in dense]
+    bms = G.register(streams, n_bits)
+    codes = [0, E.variant_code(True, 8, 8, gate=1), E.variant_code(True, 8, 8, gate=2),
+             E.variant_code(True, 128, 255, gate=1), E.variant_code(False, 0, 0)]
+    try:
+        for T in (2, 3, 4):
+            want, _ = O.threshold(streams, n_bits, T, want_hist=False)
+            for v in codes:
+                assert np.array_equal(G.gpu_threshold(bms, T, variant=v), want), ("single", T, v)
+            qs = [(np.arange(6, dtype=np.uint32), T), (np.array([0, 1, 2, 3], dtype=np.uint32), T),
+                  (np.array([0, 2, 4], dtype=np.uint32), T)]
+            wants = [O.threshold([streams[i] for i in idx], n_bits, t, want_hist=False)[0] for idx, t in qs]
+            outs, ns, caps = [], [], []
+            for idx, _ in qs:
+                o, n, c = G.alloc_out(n_bits, int(sum(len(streams[i]) for i in idx)))
+                outs.append(o); ns.append(n); caps.append(c)
+            batch = E.Batch(bms, qs, [o.data_ptr() for o in outs], caps, [n.data_ptr() for n in ns], use_graph=True)
+            try:
+                for v in codes:
+                    batch.set_variants(np.full(len(qs), v, dtype=np.uint32))
+                    _say(f"8-row bounds: T={T}, variant {v:#x}")
+                    batch.run()
+                    torch.cuda.synchronize()
+                    assert E.device_errors() == 0
+                    for i, (idx, t) in enumerate(qs):
+                        assert np.array_equal(G.fetch(outs[i], ns[i]), wants[i]), ("batched", T, v, i)
+            finally:
+                batch.free()
     finally:
         for b in bms:
             b.release()
