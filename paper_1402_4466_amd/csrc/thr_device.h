@@ -57,14 +57,14 @@ constexpr int TW = EWT_TILE_WORDS;    // tile width in uncompressed 64-bit words
 constexpr int BLOCK = EWT_TILE_WORDS; // threads per workgroup (one per word position of a tile)
 constexpr int NWAVES = BLOCK / 64;
 // Presence records (upper bounds on row counts): which groups of rows of a tile an
-// input can hold a one in.  Two granularities are kept: quarters of a word (16 rows),
-// used by queries of up to PCAP_FINE inputs, and groups of 4 words, used by wider
-// queries.  Either way the tile routine prunes whole words (NG_FINE groups of one word).
+// input can hold a one in.  Two kinds are kept: fine records (quarters of a word, 16 rows,
+// then 8-row groups for the words the quarters leave in play), used by queries of up to
+// 256 inputs, and groups of 4 words, used by wider queries.  Either way the tile routine
+// prunes whole words (NG_FINE groups of one word).
 constexpr int GW_COARSE = 4;
 constexpr int NG_FINE = TW;                   // groups per tile, single words
 constexpr int NG_COARSE = TW / GW_COARSE;     // groups per tile, 4-word groups
-constexpr int PV_FINE = NG_FINE / 128;        // 16-byte records per tile and bitmap
-constexpr int PV_COARSE = NG_COARSE / 128;
+constexpr int PV_COARSE = NG_COARSE / 128;   // 16-byte 4-word-group records per tile and bitmap
 constexpr int PMW_MAX = NG_FINE / 32;         // 32-bit words of the largest group mask
 constexpr int NQ_TILE = 4 * TW;               // quarter-word groups per tile
 constexpr int NO_TILE = 8 * TW;               // 8-row groups per tile

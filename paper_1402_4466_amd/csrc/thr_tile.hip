@@ -706,11 +706,13 @@ __device__ __forceinline__ void fine_bounds(const uint32_t* const* qptr, uint32_
     if (wave == 0) ((unsigned char*)pmw)[lane] = (unsigned char)(w8 & vmask);
 }
 
-// Staged inputs per granularity (the window list holds 16 * WCAP bytes).
-constexpr uint32_t PCAP_FINE = (uint32_t)(WCAP / PV_FINE);
+// Queries of up to PCAP_FINE inputs use the fine records (eight wavefronts take 32 inputs
+// each in the bounds passes); wider ones stage the 4-word-group records of their first
+// PCAP_COARSE inputs in the window list (16 * WCAP bytes).
+constexpr uint32_t PCAP_FINE = 256u;
 constexpr uint32_t PCAP_COARSE = (uint32_t)(WCAP / PV_COARSE);
-static_assert((NG_FINE / 4) * 4 == BLOCK && (NG_COARSE / 4) * 16 == BLOCK, "lanes per quad of groups");
-static_assert(PCAP_FINE / 4 < 256u && PCAP_COARSE / 16 < 256u, "byte counters");
+static_assert((NG_COARSE / 4) * 16 == BLOCK, "lanes per quad of groups");
+static_assert(PCAP_COARSE / 16 < 256u, "byte counters");
 static_assert(PCAP_FINE < (1u << QP) && PCAP_FINE <= 8u * 32u, "quarter counts fit QP planes, 32 inputs per wavefront");
 static_assert(7 * QP * 64 * 4 <= WCAP * 16, "quarter count scratch fits the window list");
 
@@ -751,9 +753,10 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     EWT_PHASE(0);
     for (int i = tid; i < P * TW; i += BLOCK) planes[i] = 0;
     for (int i = tid; i < TW + 8; i += BLOCK) diff[i] = 0;
-    // until the decode starts, the window list holds the presence words of the
-    // first pcap inputs (word-major: word w of input k at w * pcap + k) and the
-    // dense-row list the per-group counts
+    // until the decode starts, the window list holds the 4-word-group records of the
+    // first pcap inputs (word-major: word w of input k at w * pcap + k; wide queries) or
+    // the wavefronts' partial counters of the bounds passes (fine records), and the
+    // dense-row list the per-group counts (wide queries) or the inputs' fine records
     uint32_t* prs = (uint32_t*)win;
     uint32_t* gcnt = (uint32_t*)dense;
     const uint32_t** qptr = (const uint32_t**)dense;   // quarter records of the inputs (fine presence)
