@@ -65,7 +65,7 @@ typedef struct {
     uint64_t one_fill_words;   /* uncompressed words covered by fills of ones */
     uint64_t popcount;         /* number of rows set (|B_i|) */
     uint64_t run_count;        /* RunCount: runs of 0s and 1s over the r rows (Section 3.1) */
-    uint64_t index_bytes;      /* device bytes of the locator and skip index */
+    uint64_t index_bytes;      /* device bytes of the locator, skip index and presence records */
 } ewah_stats;
 
 /* Selects the HIP device (must be gfx950) and allocates library state.  Idempotent. */
@@ -81,8 +81,9 @@ const char* ewah_last_error(void);
  * every tile of 512 uncompressed words, the marker whose run covers the tile's
  * first word, with that marker word), the skip index (for every 64 compressed
  * words, which of them are markers and the position of the first one) and the
- * presence records (per tile, which words and which groups of 4 words hold a
- * dirty word or lie in a one-fill).  v->words is a host pointer if on_device == 0,
+ * presence records (per tile, which 16-row quarters and which 8-row groups of each
+ * word hold a one, and which groups of 4 words hold a dirty word or lie in a
+ * one-fill).  v->words is a host pointer if on_device == 0,
  * else a device pointer; it is only read during the call.  The call is
  * synchronous.  Limits: n_bits < 2^37 (U < 2^31 words).  EFORMAT if the stream
  * is malformed.  *out is owned by the caller until ewah_release().
