@@ -82,8 +82,8 @@ const char* ewah_last_error(void);
  * first word, with that marker word), the skip index (for every 64 compressed
  * words, which of them are markers and the position of the first one) and the
  * presence records (per tile, which 16-row quarters and which 8-row groups of each
- * word hold a one, and which groups of 4 words hold a dirty word or lie in a
- * one-fill).  v->words is a host pointer if on_device == 0,
+ * word hold a one and how many quarters hold one, and which groups of 4 words hold
+ * a dirty word or lie in a one-fill).  v->words is a host pointer if on_device == 0,
  * else a device pointer; it is only read during the call.  The call is
  * synchronous.  Limits: n_bits < 2^37 (U < 2^31 words).  EFORMAT if the stream
  * is malformed.  *out is owned by the caller until ewah_release().
@@ -321,8 +321,10 @@ ewah_status ewah_batch_get_variants(ewah_batch* b, uint32_t* variants_host);
  * of repeated runs as the true time, Section 7.5): runs the batch reps times
  * (eager launches, the batch's grid and variants) and writes, per query, the
  * minimum over the runs of the time the workgroups spent on its tiles, in
- * microseconds (device wall clock), into busy_us[nq] (host).  A persistent
- * launch takes about the sum of these times divided by its grid.  Synchronous.
+ * microseconds (device wall clock), into busy_us[nq] (host).  The bounds
+ * pre-pass's wavefronts count at the share of a CU they hold relative to a
+ * workgroup of the tile routine.  A persistent launch takes about the sum of
+ * these times divided by its grid.  Synchronous.
  */
 ewah_status ewah_batch_time_queries(ewah_batch* b, uint32_t reps, float* busy_us, void* hip_stream);
 

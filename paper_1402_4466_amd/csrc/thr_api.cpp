@@ -125,8 +125,9 @@ struct Built {
     std::vector<uint4> loc;    // per tile boundary: covering marker index, its run start, the marker word
     std::vector<uint4> desc;   // per CHUNK words: marker mask (lo, hi), position of the chunk's first word
     std::vector<uint4> pres;   // per tile PV_COARSE records: 4-word groups holding a dirty word or a one-fill
-    std::vector<uint32_t> presq;   // per tile PQ_WORDS words: quarter-word groups holding a one, their count,
-                                   // 8-row groups holding a one
+    std::vector<uint32_t> presq;   // per tile PQ_WORDS words: quarter-word groups holding a one, 8-row groups
+                                   // holding a one
+    std::vector<uint16_t> qcnt;    // per tile: number of quarter-word groups holding a one
     ewah_stats st{};
 };
 
@@ -226,7 +227,9 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
     if (tiles) b.loc[tiles] = make_uint4((uint32_t)nw, (uint32_t)U, 0, 0);
     // per tile: the quarter bits and their count, and the word bits ORed over each group of 4 words
     b.presq.assign(tiles * PQ_WORDS, 0u);
+    b.qcnt.assign(tiles, 0u);
     b.pres.assign(tiles * PV_COARSE, make_uint4(0, 0, 0, 0));
+    static_assert(NQ_TILE < 65536, "quarter counts fit 16 bits");
     static_assert(TW % 64 == 0 && GW_COARSE == 4, "presence record packing");
     for (uint64_t t = 0; t < tiles; ++t) {
         const uint64_t* qw = qbits.data() + t * (NQ_TILE / 64);
@@ -237,7 +240,7 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
             rec[2 * k + 1] = (uint32_t)(qw[k] >> 32);
             nq += (uint32_t)popc64(qw[k]);
         }
-        rec[NQ_TILE / 32] = nq;
+        b.qcnt[t] = (uint16_t)nq;
         const uint64_t* ow = obits.data() + t * (NO_TILE / 64);
         for (int k = 0; k < NO_TILE / 64; ++k) {
             rec[PQ_OCT + 2 * k] = (uint32_t)ow[k];
@@ -255,7 +258,8 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
         for (int v = 0; v < PV_COARSE; ++v)
             b.pres[t * PV_COARSE + v] = make_uint4(c[4 * v], c[4 * v + 1], c[4 * v + 2], c[4 * v + 3]);
     }
-    st.index_bytes = (b.loc.size() + b.desc.size() + b.pres.size()) * sizeof(uint4) + b.presq.size() * 4;
+    st.index_bytes = (b.loc.size() + b.desc.size() + b.pres.size()) * sizeof(uint4) + b.presq.size() * 4 +
+                     b.qcnt.size() * 2;
     return EWAH_OK;
 }
 
@@ -467,7 +471,7 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
     // skip index | locator | 4-word-group presence | quarter-word presence], each part 256-byte aligned.  The image is assembled on the host
     // and uploaded in pieces of at most kStage bytes.
     constexpr size_t kStage = 256ull << 20;
-    struct Layout { size_t words, desc, loc, pres, presq, end; };
+    struct Layout { size_t words, desc, loc, pres, presq, qcnt, end; };
     std::vector<Layout> lay(count);
     size_t total = 0;
     for (uint32_t i = 0; i < count; ++i) {
@@ -478,7 +482,8 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
         l.loc = l.desc + align256(nch * 16);
         l.pres = l.loc + align256(built[i].loc.size() * 16);
         l.presq = l.pres + align256(std::max<size_t>(built[i].pres.size(), 1) * 16);
-        l.end = l.presq + align256(std::max<size_t>(built[i].presq.size(), 1) * 4);
+        l.qcnt = l.presq + align256(std::max<size_t>(built[i].presq.size(), 1) * 4);
+        l.end = l.qcnt + align256(std::max<size_t>(built[i].qcnt.size(), 1) * 2);
         total = l.end;
     }
     Arena* arena = new Arena();
@@ -507,6 +512,8 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
                 std::memcpy(stage.data() + (lay[i].pres - base), built[i].pres.data(), built[i].pres.size() * 16);
             if (!built[i].presq.empty())
                 std::memcpy(stage.data() + (lay[i].presq - base), built[i].presq.data(), built[i].presq.size() * 4);
+            if (!built[i].qcnt.empty())
+                std::memcpy(stage.data() + (lay[i].qcnt - base), built[i].qcnt.data(), built[i].qcnt.size() * 2);
         }
         HIPCHK(hipMemcpy((char*)arena->d + base, stage.data(), len, hipMemcpyHostToDevice));
         i0 = i1;
@@ -519,6 +526,7 @@ ewah_status ewah_register_many(const ewah_view* v, uint32_t count, int on_device
         b->dev.desc = (const uint4*)(base + lay[i].desc);
         b->dev.pres = (const uint4*)(base + lay[i].pres);
         b->dev.presq = (const uint32_t*)(base + lay[i].presq);
+        b->dev.qcnt = (const uint16_t*)(base + lay[i].qcnt);
         b->dev.n_words = (uint32_t)v[i].n_words;
         b->dev.U = (uint32_t)((v[i].n_bits + 63) / 64);
         b->stats = built[i].st;
@@ -945,6 +953,8 @@ struct ewah_batch {
     float* d_feat = nullptr;       // features [nq][16] and predictions [nq][16] of ewah_batch_select_model
     float* d_pred = nullptr;
     uint32_t* d_itemt = nullptr;   // per-item busy ticks of ewah_batch_time_queries
+    uint32_t* d_pre = nullptr;     // per item: result of the bounds pre-pass (PRE_*)
+    uint32_t* d_pmask = nullptr;   // per item: PRE_MASK_WORDS words of its word mask
     std::vector<uint32_t> h_codes; // their host copy (upload only on change)
     uint64_t n_bits = 0;
     uint32_t nq = 0;
@@ -967,7 +977,7 @@ ewah_status batch_build_graph(ewah_batch* b) {
     HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = launch_bump(b->d_work, b->cap_stream);
     hipError_t e2 = launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1,
-                                 g.d_err, b->grid, b->smem, b->cap_stream, nullptr, b->win_batch);
+                                 g.d_err, b->grid, b->smem, b->cap_stream, nullptr, b->win_batch, b->d_pre, b->d_pmask);
     hipError_t e3 = hipStreamEndCapture(b->cap_stream, &b->graph);
     HIPCHK(e1);
     HIPCHK(e2);
@@ -1043,6 +1053,8 @@ ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, con
     }
     HIPCHK(hipMalloc(&b->d_qtile, (nq + 1) * 4));
     HIPCHK(hipMemcpy(b->d_qtile, qtile.data(), (nq + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMalloc(&b->d_pre, (size_t)qtile[nq] * 4));
+    HIPCHK(hipMalloc(&b->d_pmask, (size_t)qtile[nq] * PRE_MASK_WORDS * 4));
     HIPCHK(hipMalloc(&b->d_work, WORK_WORDS * 4));
     HIPCHK(hipMemset(b->d_work, 0, WORK_WORDS * 4));
     HIPCHK(hipMalloc(&b->d_codes, 64 * 4));
@@ -1084,7 +1096,7 @@ ewah_status ewah_batch_run(ewah_batch* b, void* hip_stream) {
     } else {
         HIPCHK(launch_bump(b->d_work, s));
         HIPCHK(launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1, g.d_err,
-                            b->grid, b->smem, s, nullptr, b->win_batch));
+                            b->grid, b->smem, s, nullptr, b->win_batch, b->d_pre, b->d_pmask));
     }
     return EWAH_OK;
 }
@@ -1129,6 +1141,8 @@ void ewah_batch_free(ewah_batch* b) {
     if (b->d_feat) (void)hipFree(b->d_feat);
     if (b->d_pred) (void)hipFree(b->d_pred);
     if (b->d_itemt) (void)hipFree(b->d_itemt);
+    (void)hipFree(b->d_pre);
+    (void)hipFree(b->d_pmask);
     delete b;
 }
 
@@ -1214,24 +1228,30 @@ ewah_status ewah_batch_select_model(ewah_batch* b, const ewah_selector* sel, int
 ewah_status ewah_batch_time_queries(ewah_batch* b, uint32_t reps, float* busy_us, void* hip_stream) {
     if (!b || !busy_us || reps == 0) return fail(EWAH_EINVAL, "bad arguments");
     hipStream_t s = (hipStream_t)hip_stream;
-    if (!b->d_itemt) HIPCHK(hipMalloc(&b->d_itemt, std::max<size_t>(b->total, 1) * 4));
+    if (!b->d_itemt) HIPCHK(hipMalloc(&b->d_itemt, std::max<size_t>(2 * (size_t)b->total, 1) * 4));
     int khz = 0;
     HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g.device));
     if (khz <= 0) return fail(EWAH_EDEVICE, "device reports no wall-clock rate");
     std::vector<uint32_t> qtile(b->nq + 1);
     HIPCHK(hipMemcpy(qtile.data(), b->d_qtile, (b->nq + 1) * 4, hipMemcpyDeviceToHost));
-    std::vector<uint32_t> ticks(b->total);
+    std::vector<uint32_t> ticks(2 * (size_t)b->total);
     std::vector<double> best(b->nq, 1e300);
+    // a pre-pass wavefront holds 1 / pre_waves_per_cu of a CU, a workgroup of the tile routine
+    // 1 / batch_blocks_per_cu: its ticks count at that ratio
+    const double wpre = (double)batch_blocks_per_cu(b->smem) / (double)pre_waves_per_cu();
     for (uint32_t r = 0; r < reps; ++r) {
         HIPCHK(launch_bump(b->d_work, s));
         HIPCHK(launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1, g.d_err,
-                            b->grid, b->smem, s, b->d_itemt, b->win_batch));
-        HIPCHK(hipMemcpyAsync(ticks.data(), b->d_itemt, (size_t)b->total * 4, hipMemcpyDeviceToHost, s));
+                            b->grid, b->smem, s, b->d_itemt, b->win_batch, b->d_pre, b->d_pmask));
+        HIPCHK(hipMemcpyAsync(ticks.data(), b->d_itemt, 2 * (size_t)b->total * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         for (uint32_t q = 0; q < b->nq; ++q) {
-            double t = 0;
-            for (uint32_t i = qtile[q]; i < qtile[q + 1]; ++i) t += ticks[i];
-            best[q] = std::min(best[q], t);
+            double t = 0, tp = 0;
+            for (uint32_t i = qtile[q]; i < qtile[q + 1]; ++i) {
+                t += ticks[i];
+                tp += ticks[(size_t)b->total + i];
+            }
+            best[q] = std::min(best[q], t + wpre * tp);
         }
     }
     for (uint32_t q = 0; q < b->nq; ++q) busy_us[q] = (float)(best[q] * 1e3 / khz);

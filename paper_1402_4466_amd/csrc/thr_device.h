@@ -89,9 +89,11 @@ struct BitmapDev {
                              // tile hold a dirty word or a one-fill (the input can contribute there)
     const uint32_t* presq;   // per tile PQ_WORDS words: in words 0 .. NQ_TILE / 32 - 1, bit 4w + j set
                              // iff rows [16j, 16j + 16) of word w of the tile hold a one (a one-fill,
-                             // or a nonzero quarter of a dirty word); word NQ_TILE / 32: how many
-                             // such quarters the tile has; from word PQ_OCT, bit 8w + j set iff
-                             // rows [8j, 8j + 8) of word w hold a one
+                             // or a nonzero quarter of a dirty word); words NQ_TILE / 32 .. PQ_OCT - 1
+                             // unused; from word PQ_OCT, bit 8w + j set iff rows [8j, 8j + 8) of
+                             // word w hold a one
+    const uint16_t* qcnt;    // per tile: how many quarter-word groups of the tile hold a one (the
+                             // tiles of a bitmap side by side, so neighbouring tiles share lines)
 };
 
 // Associative run-structure aggregate of a range of output words (see encode step).
@@ -239,6 +241,18 @@ constexpr int WORK_CTR = 16, WORK_STRIDE = 16;
 constexpr int WORK_WORDS = WORK_CTR + WORK_STRIDE * NXCD;
 constexpr int STAGE_WORDS = TW + 8;   // staged output words per tile (at most TW + 1 are used)
 
+// Bounds pre-pass of a batched launch: per item (query, tile) one result word and a word mask
+// of PRE_MASK_WORDS words (bit w: every row count of word w of the tile is below T).
+enum : uint32_t {
+    PRE_NONE = 0,      // not evaluated (queries of more than PCAP_FINE inputs, trivial T): the tile
+                       // routine takes its own count bounds
+    PRE_SETTLED = 1,   // every row count of the tile is below T: its aggregate is published
+    PRE_OPEN = 2,      // evaluated, no word pruned (or the gate kept the records unread)
+    PRE_MASK = 3,      // evaluated, the words of the mask are pruned
+};
+constexpr int PRE_MASK_WORDS = TW / 32;
+constexpr uint32_t CLAIM_ITEMS = 4;   // items a workgroup of the batched launch claims at once
+
 // LDS bytes needed by the tile routine for a query with N inputs.
 __host__ __device__ inline size_t tile_smem_bytes(uint32_t N) {
     size_t P = (size_t)planes_for(N);
@@ -264,12 +278,17 @@ hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* tic
                         const InlineIds* ids = nullptr);
 hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_t* tq, uint32_t nq, uint32_t total,
                         const BitmapDev* table, uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid,
-                        size_t smem, hipStream_t s, uint32_t* item_t = nullptr,   // item_t: per-item busy time
-                        int win_batch = 7);   // windows per wavefront batch: 4..7
+                        size_t smem, hipStream_t s,
+                        uint32_t* item_t = nullptr,  // 2 * total words: per-item busy ticks of the tile routine, then
+                                                     // of the pre-pass wavefront (null: not timed)
+                        int win_batch = 7,    // windows per wavefront batch: 4..7
+                        uint32_t* pre = nullptr,     // total words: bounds pre-pass results (null: none)
+                        uint32_t* pmask = nullptr);  // total * PRE_MASK_WORDS words: its word masks
 hipError_t launch_bump(uint32_t* work, hipStream_t s);   // epoch at work[1], counters cleared
 hipError_t launch_zero_len(uint64_t* out_n, hipStream_t s);
 hipError_t set_smem_limits(size_t max_bytes);
 int batch_blocks_per_cu(size_t smem);   // resident workgroups of the batched kernel per CU
+int pre_waves_per_cu();                  // resident wavefronts of the bounds pre-pass per CU
 hipError_t launch_features(const QueryDev* qs, uint32_t nq, const float4* stats, float r, float* feat, hipStream_t s);
 hipError_t launch_select(const float* pred, uint32_t nq, uint32_t n_arms, const uint32_t* codes, QueryDev* qs,
                          hipStream_t s);

@@ -256,9 +256,13 @@ __device__ __forceinline__ void lit_lane(const EWT_GLOBAL uint64_t* words, uint3
 
 // Per-lane select by a wave-uniform lane mask held in scalar registers:
 // bit `lane` of mask set -> b, else a (one v_cndmask with the mask as its
-// condition operand).
+// condition operand).  The mask is passed through readfirstlane, which costs
+// nothing where it already sits in scalar registers and keeps the operand a
+// scalar pair where the compiler cannot prove it uniform.
 __device__ __forceinline__ uint32_t lane_sel(uint64_t mask, uint32_t a, uint32_t b) {
     uint32_t r;
+    mask = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(mask >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)mask);
     asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(mask));
     return r;
 }
@@ -585,6 +589,44 @@ __device__ __forceinline__ void csa(uint32_t& h, uint32_t& l, uint32_t a, uint32
     l = u ^ c;
 }
 
+// Adds eight 32-bit masks into the bit-sliced counter c (QP planes): bit j of each mask adds
+// one to the count of position j (a carry-save tree of the eight, then one ripple).
+__device__ __forceinline__ void add8(uint32_t* c, const uint32_t* y) {
+    uint32_t h1, l1, h2, l2, h3, l3, g1, m1;
+    csa(h1, l1, y[0], y[1], y[2]);
+    csa(h2, l2, l1, y[3], y[4]);
+    csa(h3, l3, l2, y[5], y[6]);
+    const uint32_t o = l3 ^ y[7], h4 = l3 & y[7];
+    csa(g1, m1, h1, h2, h3);
+    const uint32_t tw = m1 ^ h4, g2 = m1 & h4;
+    const uint32_t f = g1 ^ g2, e = g1 & g2;
+    // counter += o + 2 tw + 4 f + 8 e
+    uint32_t cy = c[0] & o;
+    c[0] ^= o;
+    uint32_t u;
+    u = c[1] ^ tw; { const uint32_t n = (c[1] & tw) | (u & cy); c[1] = u ^ cy; cy = n; }
+    u = c[2] ^ f;  { const uint32_t n = (c[2] & f) | (u & cy); c[2] = u ^ cy; cy = n; }
+    u = c[3] ^ e;  { const uint32_t n = (c[3] & e) | (u & cy); c[3] = u ^ cy; cy = n; }
+#pragma unroll
+    for (int p = 4; p < QP; ++p) {
+        const uint32_t n = c[p] & cy;
+        c[p] ^= cy;
+        cy = n;
+    }
+}
+
+// Positions whose count in the bit-sliced counter c is below tz, most significant plane first.
+__device__ __forceinline__ uint32_t below(const uint32_t* c, uint32_t tz) {
+    uint32_t gt = 0u, eq = ~0u;
+#pragma unroll
+    for (int p = QP - 1; p >= 0; --p) {
+        const uint32_t tb = ((tz >> p) & 1u) ? ~0u : 0u;
+        gt |= eq & c[p] & ~tb;
+        eq &= ~(c[p] ^ tb);
+    }
+    return (tz >> QP) ? ~0u : ~(gt | eq);
+}
+
 __device__ __forceinline__ uint32_t bound_pass(const uint32_t* const* qptr, uint32_t N, uint32_t off, bool skip,
                                                uint32_t tz, uint32_t* part) {
     const int lane = __lane_id();
@@ -603,28 +645,7 @@ __device__ __forceinline__ uint32_t bound_pass(const uint32_t* const* qptr, uint
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         if ((uint32_t)(8 * g) >= ni) break;
-        const uint32_t* y = x + 8 * g;
-        uint32_t h1, l1, h2, l2, h3, l3, g1, m1;
-        csa(h1, l1, y[0], y[1], y[2]);
-        csa(h2, l2, l1, y[3], y[4]);
-        csa(h3, l3, l2, y[5], y[6]);
-        const uint32_t o = l3 ^ y[7], h4 = l3 & y[7];
-        csa(g1, m1, h1, h2, h3);
-        const uint32_t tw = m1 ^ h4, g2 = m1 & h4;
-        const uint32_t f = g1 ^ g2, e = g1 & g2;
-        // counter += o + 2 tw + 4 f + 8 e
-        uint32_t cy = c[0] & o;
-        c[0] ^= o;
-        uint32_t u;
-        u = c[1] ^ tw; { const uint32_t n = (c[1] & tw) | (u & cy); c[1] = u ^ cy; cy = n; }
-        u = c[2] ^ f;  { const uint32_t n = (c[2] & f) | (u & cy); c[2] = u ^ cy; cy = n; }
-        u = c[3] ^ e;  { const uint32_t n = (c[3] & e) | (u & cy); c[3] = u ^ cy; cy = n; }
-#pragma unroll
-        for (int p = 4; p < QP; ++p) {
-            const uint32_t n = c[p] & cy;
-            c[p] ^= cy;
-            cy = n;
-        }
+        add8(c, x + 8 * g);
     }
     // wavefronts w + s add into w (s = 4, 2, 1), each round in its own part of the scratch
     uint32_t po = 0;
@@ -648,15 +669,7 @@ __device__ __forceinline__ uint32_t bound_pass(const uint32_t* const* qptr, uint
         }
         po += sft * QP * 64u;
     }
-    // groups below tz, most significant plane first (wavefront 0 holds the sums)
-    uint32_t gt = 0u, eq = ~0u;
-#pragma unroll
-    for (int p = QP - 1; p >= 0; --p) {
-        const uint32_t tb = ((tz >> p) & 1u) ? ~0u : 0u;
-        gt |= eq & c[p] & ~tb;
-        eq &= ~(c[p] ^ tb);
-    }
-    return (tz >> QP) ? ~0u : ~(gt | eq);
+    return below(c, tz);   // groups below tz (wavefront 0 holds the sums)
 }
 
 // Word mask of a tile of a query of at most PCAP_FINE inputs, as bytes at pmw (byte l: words
@@ -730,7 +743,8 @@ static_assert((MAXN + 1u) * 4u <= (uint32_t)WCAP * 16u, "count histogram must fi
 template <bool STAGED, bool GENERAL = false, bool MAXC = false, bool LOOPED = false, bool HIST = false,
           int WB = WIN_BATCH>
 __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ table, uint32_t t,
-                             uint32_t epoch, unsigned char* smem, uint32_t* err, uint32_t dbg_slot) {
+                             uint32_t epoch, unsigned char* smem, uint32_t* err, uint32_t dbg_slot,
+                             uint32_t pre = PRE_NONE, const uint32_t* pmask = nullptr) {
     (void)dbg_slot;   // timestamp slot of debug builds
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wavefront
@@ -793,6 +807,8 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     const uint32_t ngv = (nPos + (1u << gsh) - 1u) >> gsh;   // groups inside the tile
     // presence groups an input touching all of the tile has: quarters, or 4-word groups
     const uint32_t nfull = fine ? 4u * nPos : ngv;
+    // word mask of the bounds pre-pass (stored with the classify step's counters)
+    const uint32_t pmv = (pre == PRE_MASK && tid < PRE_MASK_WORDS) ? gp(pmask)[tid] : 0u;
     if (!trivial) {
         for (uint32_t kb = 0; kb < N; kb += BLOCK) {
             uint32_t k = kb + (uint32_t)tid;
@@ -806,8 +822,9 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                 uint4 pr = make_uint4(0u, 0u, 0u, 0u);
                 uint32_t qc = 0;
                 static_assert(PV_COARSE == 1, "one 4-word-group record per tile");
-                if (fine) qc = gp(qr)[NQ_TILE / 32];
-                else pr = gp(B.pres)[t];
+                if (fine) {
+                    if (pre == PRE_NONE) qc = gp(B.qcnt)[t];   // else the pre-pass took the bounds
+                } else pr = gp(B.pres)[t];
                 Seg s = locate(B, t, tS, tE, tiles);
                 if (fine) {
                     // quarter counts; the records are read by the bounds step
@@ -838,6 +855,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
             }
         }
     }
+    if (pre == PRE_MASK && tid < PRE_MASK_WORDS) misc[M_PR + tid] = pmv;
     __syncthreads();
     EWT_PHASE(1);
     // every row count of the tile lies in [full one-fills, inputs that can hold a one]
@@ -892,8 +910,10 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     pm.on = false;
     const uint32_t gate = (q.variant >> VAR_GATE_SHIFT) & 3u;
     const uint64_t gnum = gate == GATE_1_5 ? 15ull : 11ull;
-    if (mode == 0 && misc[M_DFULL] < Tz && gate != GATE_NEVER &&
-        (gate == GATE_ALWAYS || 10ull * Tz * nfull > gnum * misc[M_PSUM])) {
+    if (pre != PRE_NONE) {
+        pm.on = pre == PRE_MASK;   // bounds of the pre-pass (a tile it settled never gets here)
+    } else if (mode == 0 && misc[M_DFULL] < Tz && gate != GATE_NEVER &&
+               (gate == GATE_ALWAYS || 10ull * Tz * nfull > gnum * misc[M_PSUM])) {
         if (fine) fine_bounds(qptr, N, Tz, nPos, prs, misc + M_PR, misc + M_TMP);
         else count_quads<16>(prs, PCAP_COARSE, min(N, PCAP_COARSE), gcnt);
         if (N > pcap) {   // the rest of very wide queries (4-word groups): wavefront ballots
@@ -1432,6 +1452,146 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
     EWT_PHASE(7);
 }
 
+// ------------------------------------------------------------ bounds pre-pass
+
+// Adds, for every input k < N of a query, word off of its presence record of the tile into the
+// bit-sliced counter c (one wavefront; lane 64 r + i of round r holds input k's record at rp[r];
+// lanes with skip set load nothing).  32 loads are in flight before any is added.
+__device__ __forceinline__ void count_records(const uint32_t* const* rp, uint32_t N, uint32_t off, bool skip,
+                                              uint32_t* c) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if ((uint32_t)(64 * r) >= N) break;
+        const uint64_t base = (uint64_t)(uintptr_t)rp[r];
+        const int blo = (int)(uint32_t)base, bhi = (int)(uint32_t)(base >> 32);
+#pragma unroll 1
+        for (uint32_t j0 = 0; j0 < 64u && 64u * (uint32_t)r + j0 < N; j0 += 32u) {
+            const uint32_t ni = min(32u, N - 64u * (uint32_t)r - j0);
+            uint32_t x[32];
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                x[i] = 0u;
+                if ((uint32_t)i < ni && !skip) {
+                    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(blo, (int)j0 + i);
+                    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(bhi, (int)j0 + i);
+                    x[i] = gp((const uint32_t*)(uintptr_t)(((uint64_t)hi << 32) | lo))[off];
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                if ((uint32_t)(8 * g) >= ni) break;
+                add8(c, x + 8 * g);
+            }
+        }
+    }
+}
+
+// Count bounds of one item (query q, tile t) of a batch, by one wavefront with no barrier:
+// what the tile routine's classify and bounds steps take from the presence records (RBMrg's
+// pruning by count bounds, Section 5.2), for threshold queries of at most PCAP_FINE inputs.
+// A tile whose row counts are all below T publishes its aggregate here (a zero fill; the
+// placement pass writes its marker) and never takes a workgroup of the batched launch.
+// Returns PRE_*; PRE_MASK leaves the word mask at mask.  Lanes must all be active.
+__device__ uint32_t pre_bounds(const QueryDev& q, uint32_t t, uint32_t epoch, uint32_t* mask) {
+    const int lane = __lane_id();
+    const uint32_t N = q.N, T = q.T;
+    if (N > PCAP_FINE || T == 0u || T > N || q.pd || !q.bms) return PRE_NONE;
+    const uint32_t tS = t * (uint32_t)TW;
+    const uint32_t nPos = min((uint32_t)TW, q.U - tS);
+    const uint32_t nfull = 4u * nPos;   // quarters of an input with a one in every quarter
+    // input 64 r + lane: its record of the tile and how many of its quarters hold a one (all
+    // loads issued before any is used)
+    const uint32_t* rp[4];
+    const uint16_t* cp[4];
+    uint32_t qc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t k = 64u * (uint32_t)r + (uint32_t)lane;
+        rp[r] = nullptr;
+        cp[r] = nullptr;
+        if (k < N) {
+            rp[r] = gp(q.bms)[k].presq + (size_t)t * PQ_WORDS;
+            cp[r] = gp(q.bms)[k].qcnt + t;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t k = 64u * (uint32_t)r + (uint32_t)lane;
+        qc[r] = k < N ? (uint32_t)*gp(cp[r]) : 0u;
+    }
+    uint32_t psum = 0, dfull = 0, nz = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t k = 64u * (uint32_t)r + (uint32_t)lane;
+        psum += qc[r];
+        dfull += (uint32_t)__popcll(__ballot(k < N && qc[r] == nfull));
+        nz += (uint32_t)__popcll(__ballot(qc[r] != 0u));
+    }
+    psum = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(psum), 63);
+    const uint32_t gate = (q.variant >> VAR_GATE_SHIFT) & 3u;
+    const uint64_t gnum = gate == GATE_1_5 ? 15ull : 11ull;
+    bool settled = nz < T;   // fewer than T inputs have a one anywhere in the tile
+    uint32_t w8 = 0, vmask = 0;
+    if (!settled) {
+        // the gate of the tile routine: bounds only where they are likely to prune
+        if (dfull >= T || gate == GATE_NEVER || (gate != GATE_ALWAYS && 10ull * T * nfull <= gnum * psum))
+            return PRE_OPEN;
+        // quarters (lane l: quarters 32 l .. 32 l + 31, four per word), then the 8-row groups of
+        // the words still in play (record word PQ_OCT + 2 l + h: words 8 l + 4 h .. 8 l + 4 h + 3)
+        const uint32_t w0 = 8u * (uint32_t)lane;
+        vmask = (1u << (nPos > w0 ? min(nPos - w0, 8u) : 0u)) - 1u;   // words of this lane in the tile
+        uint32_t c[QP];
+#pragma unroll
+        for (int p = 0; p < QP; ++p) c[p] = 0u;
+        count_records(rp, N, (uint32_t)lane, false, c);
+        uint32_t m = below(c, T);
+        m &= m >> 1;
+        m &= m >> 2;   // bit 4 i: all four quarters of word w0 + i
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w8 |= ((m >> (4 * i)) & 1u) << i;
+        w8 &= vmask;
+#pragma unroll 1
+        for (uint32_t h = 0; h < 2u; ++h) {
+            const bool skip = ((w8 | ~vmask) >> (4u * h) & 15u) == 15u;
+            if (__ballot(!skip) == 0ull) continue;
+#pragma unroll
+            for (int p = 0; p < QP; ++p) c[p] = 0u;
+            count_records(rp, N, (uint32_t)PQ_OCT + 2u * (uint32_t)lane + h, skip, c);
+            uint32_t o = below(c, T);
+            o &= o >> 1;
+            o &= o >> 2;
+            o &= o >> 4;   // bit 8 i: all eight 8-row groups of word w0 + 4 h + i
+            if (!skip) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w8 |= ((o >> (8 * i)) & 1u) << (4u * h + (uint32_t)i);
+            }
+        }
+        w8 &= vmask;
+        settled = __ballot(w8 != vmask) == 0ull;
+    }
+    if (settled) {
+        if (lane == 0) {
+            EWT_GLOBAL TileState* st = gp(q.state);
+            Agg A;
+            A.n = 1;
+            A.lh_pos = tS;
+            A.lh_out = 0;
+            A.bits = 1u << 4;   // one head, a zero fill
+            st[t].head[0] = 0ull;
+            st[t].head[1] = 1ull << 16;
+            agg_publish(st[t].local, A, epoch);
+        }
+        return PRE_SETTLED;
+    }
+    if (__ballot(w8 != 0u) == 0ull) return PRE_OPEN;
+    // byte l of the mask: words 8 l .. 8 l + 7
+    uint32_t v = w8 << (8u * ((uint32_t)lane & 3u));
+    v |= (uint32_t)__shfl_xor((int)v, 1, 64);
+    v |= (uint32_t)__shfl_xor((int)v, 2, 64);
+    if ((lane & 3) == 0) gp(mask)[lane >> 2] = v;
+    return PRE_MASK;
+}
+
 // ------------------------------------------------------------ output placement
 
 // Exclusive prefix of the tile aggregates of one query (one workgroup of
@@ -1657,42 +1817,81 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_max_kernel(QueryDev q, con
 // turn.  qtile[i] = first item of query i (qtile[nq] = total); tq[i] = query of item i.
 // item_t (null: off): per item, the wall-clock ticks its workgroup spent on it, the
 // measure of each query's cost inside a batch.
+// Bounds pre-pass of a batch: one wavefront per item.
+__global__ __launch_bounds__(256) void thr_bounds_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
+                                                          const uint32_t* __restrict__ tq, uint32_t nq, uint32_t total,
+                                                          const uint32_t* epoch_ptr, uint32_t* __restrict__ pre,
+                                                          uint32_t* __restrict__ pmask, uint32_t* __restrict__ item_t) {
+    const uint32_t it = blockIdx.x * 4u + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (it >= total) return;
+    const uint64_t t0 = item_t ? wall_clock64() : 0ull;
+    const uint32_t qi = nq > 1u ? tq[it] : 0u;
+    const QueryDev q = qs[qi];
+    const uint32_t r = pre_bounds(q, it - qtile[qi], *epoch_ptr, pmask + (size_t)it * PRE_MASK_WORDS);
+    if (__lane_id() == 0) {
+        pre[it] = r;
+        if (item_t) item_t[it] = (uint32_t)(wall_clock64() - t0);
+    }
+}
+
 template <int WB>
 __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
                                                           const uint32_t* __restrict__ tq, uint32_t nq,
                                                           const BitmapDev* __restrict__ table,
                                                           uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err,
-                                                          uint32_t* __restrict__ item_t) {
+                                                          uint32_t* __restrict__ item_t, const uint32_t* __restrict__ pre,
+                                                          const uint32_t* __restrict__ pmask) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t s_item, s_q;
+    __shared__ uint32_t s_item, s_n, s_q[CLAIM_ITEMS], s_pre[CLAIM_ITEMS];
     const uint32_t total = qtile[nq];
     const uint32_t epoch = *epoch_ptr;
     const uint32_t x0 = blockIdx.x % (uint32_t)NXCD;
     while (true) {
-        if (threadIdx.x == 0) {
-            uint32_t it = total;   // none left
-            for (uint32_t d = 0; d < (uint32_t)NXCD; ++d) {
-                const uint32_t x = (x0 + d) % (uint32_t)NXCD;
-                const uint32_t lo = (uint32_t)((uint64_t)total * x / NXCD);
-                const uint32_t hi = (uint32_t)((uint64_t)total * (x + 1u) / NXCD);
-                if (lo == hi) continue;
-                const uint32_t c = atomicAdd(&work[WORK_CTR + WORK_STRIDE * x], 1u);
-                if (c < hi - lo) { it = lo + c; break; }
+        // wavefront 0 claims a run of up to CLAIM_ITEMS items and reads their queries and
+        // pre-pass results
+        if (threadIdx.x < 64) {
+            uint32_t it = total, n = 0;
+            if (threadIdx.x == 0) {
+                for (uint32_t d = 0; d < (uint32_t)NXCD; ++d) {
+                    const uint32_t x = (x0 + d) % (uint32_t)NXCD;
+                    const uint32_t lo = (uint32_t)((uint64_t)total * x / NXCD);
+                    const uint32_t hi = (uint32_t)((uint64_t)total * (x + 1u) / NXCD);
+                    if (lo == hi) continue;
+                    const uint32_t c = atomicAdd(&work[WORK_CTR + WORK_STRIDE * x], CLAIM_ITEMS);
+                    if (c < hi - lo) { it = lo + c; n = min(CLAIM_ITEMS, hi - lo - c); break; }
+                }
             }
-            s_item = it;
-            s_q = (it < total && nq > 1u) ? tq[it] : 0u;   // query of the item (one load; a batch of one needs none)
+            it = (uint32_t)__builtin_amdgcn_readfirstlane((int)it);
+            n = (uint32_t)__builtin_amdgcn_readfirstlane((int)n);
+            const uint32_t j = threadIdx.x;
+            if (j < n) {
+                s_q[j] = nq > 1u ? tq[it + j] : 0u;   // query of the item (a batch of one needs none)
+                s_pre[j] = pre ? pre[it + j] : PRE_NONE;
+            }
+            if (j == 0) { s_item = it; s_n = n; }
         }
         __syncthreads();
         // uniform: the query record is then read into scalar registers
-        const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_item);
-        const uint32_t qi = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_q);
-        if (it >= total) break;
-        const uint64_t t0 = item_t ? wall_clock64() : 0ull;
-        QueryDev q = qs[qi];
-        if (use_looped(q.variant, q.N, q.T))
-            process_tile<true, false, false, true, false, WB>(q, table, it - qtile[qi], epoch, smem, err, it);
-        else process_tile<true, false, false, false, false, WB>(q, table, it - qtile[qi], epoch, smem, err, it);
-        if (item_t && threadIdx.x == 0) item_t[it] = (uint32_t)(wall_clock64() - t0);
+        const uint32_t it0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_item);
+        const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_n);
+        if (it0 >= total) break;
+        for (uint32_t j = 0; j < n; ++j) {
+            const uint32_t it = it0 + j;
+            const uint32_t pj = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pre[j]);
+            if (pj == PRE_SETTLED) {   // done by the pre-pass
+                if (item_t && threadIdx.x == 0) item_t[it] = 0u;
+                continue;
+            }
+            const uint32_t qi = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_q[j]);
+            const uint64_t t0 = item_t ? wall_clock64() : 0ull;
+            QueryDev q = qs[qi];
+            const uint32_t* pm = pmask ? pmask + (size_t)it * PRE_MASK_WORDS : nullptr;
+            if (use_looped(q.variant, q.N, q.T))
+                process_tile<true, false, false, true, false, WB>(q, table, it - qtile[qi], epoch, smem, err, it, pj, pm);
+            else process_tile<true, false, false, false, false, WB>(q, table, it - qtile[qi], epoch, smem, err, it, pj, pm);
+            if (item_t && threadIdx.x == 0) item_t[it] = (uint32_t)(wall_clock64() - t0);
+        }
+        __syncthreads();   // every wavefront is done with the claimed run before wavefront 0 rewrites it
     }
 }
 
@@ -1751,6 +1950,12 @@ hipError_t set_smem_limits(size_t max_bytes) {
     return hipSuccess;
 }
 
+int pre_waves_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)thr_bounds_kernel, 256, 0) != hipSuccess) return 4;
+    return n > 0 ? 4 * n : 4;
+}
+
 int batch_blocks_per_cu(size_t smem) {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)thr_batch_kernel<WIN_BATCH>, BLOCK, smem) != hipSuccess)
@@ -1778,16 +1983,19 @@ hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* tic
 
 hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_t* tq, uint32_t nq, uint32_t total,
                         const BitmapDev* table, uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid,
-                        size_t smem, hipStream_t s, uint32_t* item_t, int win_batch) {
+                        size_t smem, hipStream_t s, uint32_t* item_t, int win_batch, uint32_t* pre, uint32_t* pmask) {
+    if (pre)
+        hipLaunchKernelGGL(thr_bounds_kernel, dim3((total + 3) / 4), dim3(256), 0, s, qs, qtile, tq, nq, total, epoch_ptr,
+                           pre, pmask, item_t ? item_t + total : nullptr);
     switch (win_batch) {
         case 4: hipLaunchKernelGGL(thr_batch_kernel<4>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
-                                   epoch_ptr, err, item_t); break;
+                                   epoch_ptr, err, item_t, pre, pmask); break;
         case 5: hipLaunchKernelGGL(thr_batch_kernel<5>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
-                                   epoch_ptr, err, item_t); break;
+                                   epoch_ptr, err, item_t, pre, pmask); break;
         case 6: hipLaunchKernelGGL(thr_batch_kernel<6>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
-                                   epoch_ptr, err, item_t); break;
+                                   epoch_ptr, err, item_t, pre, pmask); break;
         case 7: hipLaunchKernelGGL(thr_batch_kernel<7>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
-                                   epoch_ptr, err, item_t); break;
+                                   epoch_ptr, err, item_t, pre, pmask); break;
         default: return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(scan_batch_kernel, dim3(nq), dim3(SCAN_THREADS), 0, s, qs, epoch_ptr, err);
