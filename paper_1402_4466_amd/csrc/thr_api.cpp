@@ -246,6 +246,8 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
             rec[PQ_OCT + 2 * k] = (uint32_t)ow[k];
             rec[PQ_OCT + 2 * k + 1] = (uint32_t)(ow[k] >> 32);
         }
+        for (int wd = 0; wd < TW; ++wd)   // a word holds a one iff one of its quarters does
+            if ((qw[wd / 16] >> (4 * (wd % 16))) & 15ull) rec[PQ_WB + wd / 32] |= 1u << (wd % 32);
         const uint64_t* w = gbits.data() + t * (TW / 64);
         uint32_t c[4 * PV_COARSE] = {};
         for (int k = 0; k < TW / 64; ++k) {

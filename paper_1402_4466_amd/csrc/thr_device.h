@@ -68,8 +68,11 @@ constexpr int PV_COARSE = NG_COARSE / 128;   // 16-byte 4-word-group records per
 constexpr int PMW_MAX = NG_FINE / 32;         // 32-bit words of the largest group mask
 constexpr int NQ_TILE = 4 * TW;               // quarter-word groups per tile
 constexpr int NO_TILE = 8 * TW;               // 8-row groups per tile
-constexpr int PQ_OCT = NQ_TILE / 32 + 4;      // record word where the 8-row bits start
-constexpr int PQ_WORDS = PQ_OCT + NO_TILE / 32;   // 32-bit words per tile and bitmap
+constexpr int PQ_OCT = NQ_TILE / 32;          // record word where the 8-row bits start
+constexpr int PQ_WB = PQ_OCT + NO_TILE / 32;  // record word where the per-word bits start
+constexpr int PQ_WORDS = PQ_WB + TW / 32 + 16;   // 32-bit words per tile and bitmap (a multiple of 32:
+                                                 // every record and part of one starts on a 128-byte line)
+static_assert(PQ_WORDS % 32 == 0 && PQ_OCT % 32 == 0 && PQ_WB % 16 == 0, "record alignment");
 static_assert(TW % 512 == 0 && NG_FINE <= BLOCK, "presence groups per tile");
 constexpr int CHUNK = 64;         // compressed words per skip-index entry (one wavefront)
 constexpr int MAXP = 12;          // bit planes: inputs per query < 2^12 (LDS budget)
@@ -89,9 +92,9 @@ struct BitmapDev {
                              // tile hold a dirty word or a one-fill (the input can contribute there)
     const uint32_t* presq;   // per tile PQ_WORDS words: in words 0 .. NQ_TILE / 32 - 1, bit 4w + j set
                              // iff rows [16j, 16j + 16) of word w of the tile hold a one (a one-fill,
-                             // or a nonzero quarter of a dirty word); words NQ_TILE / 32 .. PQ_OCT - 1
-                             // unused; from word PQ_OCT, bit 8w + j set iff rows [8j, 8j + 8) of
-                             // word w hold a one
+                             // or a nonzero quarter of a dirty word); from word PQ_OCT, bit 8w + j set
+                             // iff rows [8j, 8j + 8) of word w hold a one; from word PQ_WB, bit w set
+                             // iff word w holds a one; the rest is padding
     const uint16_t* qcnt;    // per tile: how many quarter-word groups of the tile hold a one (the
                              // tiles of a bitmap side by side, so neighbouring tiles share lines)
 };

@@ -1536,20 +1536,29 @@ __device__ uint32_t pre_bounds(const QueryDev& q, uint32_t t, uint32_t epoch, ui
         // the gate of the tile routine: bounds only where they are likely to prune
         if (dfull >= T || gate == GATE_NEVER || (gate != GATE_ALWAYS && 10ull * T * nfull <= gnum * psum))
             return PRE_OPEN;
-        // quarters (lane l: quarters 32 l .. 32 l + 31, four per word), then the 8-row groups of
-        // the words still in play (record word PQ_OCT + 2 l + h: words 8 l + 4 h .. 8 l + 4 h + 3)
+        // lane l takes words 8 l .. 8 l + 7: first whole words (its byte of record word
+        // PQ_WB + l / 4), then the quarters of the words still in play (record word l: quarters
+        // 32 l .. 32 l + 31, four per word), then their 8-row groups (record word
+        // PQ_OCT + 2 l + h: words 8 l + 4 h .. 8 l + 4 h + 3)
         const uint32_t w0 = 8u * (uint32_t)lane;
         vmask = (1u << (nPos > w0 ? min(nPos - w0, 8u) : 0u)) - 1u;   // words of this lane in the tile
         uint32_t c[QP];
 #pragma unroll
         for (int p = 0; p < QP; ++p) c[p] = 0u;
-        count_records(rp, N, (uint32_t)lane, false, c);
-        uint32_t m = below(c, T);
-        m &= m >> 1;
-        m &= m >> 2;   // bit 4 i: all four quarters of word w0 + i
+        count_records(rp, N, (uint32_t)PQ_WB + ((uint32_t)lane >> 2), false, c);
+        w8 = (below(c, T) >> (8u * ((uint32_t)lane & 3u))) & vmask;
+        if (__ballot(w8 != vmask) != 0ull) {
+            const bool skip = (w8 | ~vmask | ~0xFFu) == ~0u;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) w8 |= ((m >> (4 * i)) & 1u) << i;
-        w8 &= vmask;
+            for (int p = 0; p < QP; ++p) c[p] = 0u;
+            count_records(rp, N, (uint32_t)lane, skip, c);
+            uint32_t m = below(c, T);
+            m &= m >> 1;
+            m &= m >> 2;   // bit 4 i: all four quarters of word w0 + i
+#pragma unroll
+            for (int i = 0; i < 8; ++i) w8 |= ((m >> (4 * i)) & 1u) << i;
+            w8 &= vmask;
+        }
 #pragma unroll 1
         for (uint32_t h = 0; h < 2u; ++h) {
             const bool skip = ((w8 | ~vmask) >> (4u * h) & 15u) == 15u;
