@@ -242,9 +242,13 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
         }
         b.qcnt[t] = (uint16_t)nq;
         const uint64_t* ow = obits.data() + t * (NO_TILE / 64);
+        // the 32 bits of words 4 m .. 4 m + 3 (m = 2 l + h) go to record word PQ_OCT + 64 h + l:
+        // the halves of the words of lanes l = 0 .. 63 each lie together
         for (int k = 0; k < NO_TILE / 64; ++k) {
-            rec[PQ_OCT + 2 * k] = (uint32_t)ow[k];
-            rec[PQ_OCT + 2 * k + 1] = (uint32_t)(ow[k] >> 32);
+            for (int e = 0; e < 2; ++e) {
+                const int m = 2 * k + e;
+                rec[PQ_OCT + 64 * (m % 2) + m / 2] = (uint32_t)(ow[k] >> (32 * e));
+            }
         }
         for (int wd = 0; wd < TW; ++wd)   // a word holds a one iff one of its quarters does
             if ((qw[wd / 16] >> (4 * (wd % 16))) & 15ull) rec[PQ_WB + wd / 32] |= 1u << (wd % 32);

@@ -92,9 +92,9 @@ struct BitmapDev {
                              // tile hold a dirty word or a one-fill (the input can contribute there)
     const uint32_t* presq;   // per tile PQ_WORDS words: in words 0 .. NQ_TILE / 32 - 1, bit 4w + j set
                              // iff rows [16j, 16j + 16) of word w of the tile hold a one (a one-fill,
-                             // or a nonzero quarter of a dirty word); from word PQ_OCT, bit 8w + j set
-                             // iff rows [8j, 8j + 8) of word w hold a one; from word PQ_WB, bit w set
-                             // iff word w holds a one; the rest is padding
+                             // or a nonzero quarter of a dirty word); in word PQ_OCT + 64h + l, bit
+                             // 8i + j set iff rows [8j, 8j + 8) of word 8l + 4h + i hold a one; from
+                             // word PQ_WB, bit w set iff word w holds a one; the rest is padding
     const uint16_t* qcnt;    // per tile: how many quarter-word groups of the tile hold a one (the
                              // tiles of a bitmap side by side, so neighbouring tiles share lines)
 };

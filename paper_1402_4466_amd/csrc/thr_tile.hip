@@ -684,14 +684,14 @@ __device__ __forceinline__ void fine_bounds(const uint32_t* const* qptr, uint32_
     const uint32_t w0 = 8u * (uint32_t)lane;
     const uint32_t vmask = (1u << (nPos > w0 ? min(nPos - w0, 8u) : 0u)) - 1u;   // words of this lane in the tile
     // pass 0: quarters (lane l holds quarters 32l .. 32l + 31, four per word); passes 1 and 2:
-    // the 8-row groups of words w0 + 4h .. w0 + 4h + 3 (h = pass - 1), record word PQ_OCT + 2l + h,
+    // the 8-row groups of words w0 + 4h .. w0 + 4h + 3 (h = pass - 1), record word PQ_OCT + 64h + l,
     // where some of those words are still in play
     uint32_t w8 = 0;
 #pragma unroll 1
     for (uint32_t pass = 0; pass < 3; ++pass) {
         const uint32_t h = pass > 0 ? pass - 1u : 0u;
         const bool skip = pass > 0 && ((w8 | ~vmask) >> (4 * h) & 15u) == 15u;
-        const uint32_t off = pass == 0 ? (uint32_t)lane : (uint32_t)PQ_OCT + 2u * (uint32_t)lane + h;
+        const uint32_t off = pass == 0 ? (uint32_t)lane : (uint32_t)PQ_OCT + 64u * h + (uint32_t)lane;
         const uint32_t lt = bound_pass(qptr, N, off, skip, tz, part);
         if (pass == 0) {
             uint32_t m = lt & (lt >> 1);
@@ -1539,7 +1539,7 @@ __device__ uint32_t pre_bounds(const QueryDev& q, uint32_t t, uint32_t epoch, ui
         // lane l takes words 8 l .. 8 l + 7: first whole words (its byte of record word
         // PQ_WB + l / 4), then the quarters of the words still in play (record word l: quarters
         // 32 l .. 32 l + 31, four per word), then their 8-row groups (record word
-        // PQ_OCT + 2 l + h: words 8 l + 4 h .. 8 l + 4 h + 3)
+        // PQ_OCT + 64 h + l: words 8 l + 4 h .. 8 l + 4 h + 3)
         const uint32_t w0 = 8u * (uint32_t)lane;
         vmask = (1u << (nPos > w0 ? min(nPos - w0, 8u) : 0u)) - 1u;   // words of this lane in the tile
         uint32_t c[QP];
@@ -1565,7 +1565,7 @@ __device__ uint32_t pre_bounds(const QueryDev& q, uint32_t t, uint32_t epoch, ui
             if (__ballot(!skip) == 0ull) continue;
 #pragma unroll
             for (int p = 0; p < QP; ++p) c[p] = 0u;
-            count_records(rp, N, (uint32_t)PQ_OCT + 2u * (uint32_t)lane + h, skip, c);
+            count_records(rp, N, (uint32_t)PQ_OCT + 64u * h + (uint32_t)lane, skip, c);
             uint32_t o = below(c, T);
             o &= o >> 1;
             o &= o >> 2;
