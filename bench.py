@@ -196,7 +196,7 @@ def bench_c4(args, E, torch):
     if tuned:
         A.apply(batch, tuned)
     grid = int(tuned["grid"]) if tuned else pb.grid
-    win_batch = int(tuned.get("win_batch", 7)) if tuned else 7
+    win_batch = int(tuned.get("win_batch", 6)) if tuned else 6
     total_in = pb.input_bytes
 
     for _ in range(args.warmup):
@@ -286,7 +286,7 @@ def bench_c4(args, E, torch):
         "config": {"workload": f"c4: {len(qs)} queries, pool {len(pool)} EWAH bitmaps, r=2^22, "
                                "d log-uniform [1e-4,0.3], N~U[2,256], T~U[1,N]",
                    "path": "batched persistent graph launch", "selector": sel_kind, "grid": grid,
-                   "win_batch": win_batch,
+                   "win_batch": win_batch, "prepass": batch.prepass,
                    "input_bytes_per_step": total_in, "output_words_per_step": out_words},
         "bit_exact": bit_exact, "bit_exact_outputs_checked": checked,
         "selection_ms_per_plan": None if sel_ms is None else round(sel_ms, 4),
@@ -536,7 +536,7 @@ def bench_index(args, E, torch):
         ow = int(g["out_n"][g["rows"]].sum().item())
         out_words += ow
         per.append({"kind": g["kind"], "shape": g["shape"], "queries": g["queries"], "grid": b.grid,
-                    "win_batch": b.win_batch, "ms": round(gms, 4),
+                    "win_batch": b.win_batch, "prepass": b.prepass, "ms": round(gms, 4),
                     "GB/s": round(g["input_bytes"] / (gms / 1e3) / 1e9, 1), "out_words": ow})
         log(f"{g['kind']} {g['shape']}: {g['queries']} queries, {gms:.3f} ms, {per[-1]['GB/s']} GB/s")
     log(f"index workload: {ms:.3f} ms/step, {value:.1f} GB/s input")

@@ -269,9 +269,19 @@ ewah_status ewah_batch_set_variants(ewah_batch* b, const uint32_t* variants);
 ewah_status ewah_batch_set_grid(ewah_batch* b, uint32_t grid);
 
 /* Sets how many 64-word windows a wavefront decodes per batch of loads in the
- * persistent kernel (4..7, default 7; a kernel is built for each), a knob of the
+ * persistent kernel (4..7, default 6; a kernel is built for each), a knob of the
  * autotuner; results never depend on it.  Rebuilds the graph.  Synchronous. */
 ewah_status ewah_batch_set_win_batch(ewah_batch* b, uint32_t win_batch);
+
+/* Turns the bounds pre-pass of the batch on (on != 0) or off, a knob of the autotuner;
+ * results never depend on it.  With it, one wavefront per (query, tile) item of the
+ * queries of at most 256 inputs evaluates the tile's count bounds from the presence
+ * records (RBMrg's pruning, Section 5.2) in a launch of its own before the persistent
+ * launch, which then takes only the tiles those bounds leave; without it, the
+ * persistent launch evaluates them per tile.  Default: on for batches of at least
+ * 65,536 items (many items keep the pre-pass's wavefronts busy; a short batch waits
+ * for its widest query's).  Rebuilds the graph.  Synchronous. */
+ewah_status ewah_batch_set_prepass(ewah_batch* b, int on);
 
 void ewah_batch_free(ewah_batch* b);
 

@@ -961,11 +961,13 @@ struct ewah_batch {
     uint32_t* d_itemt = nullptr;   // per-item busy ticks of ewah_batch_time_queries
     uint32_t* d_pre = nullptr;     // per item: result of the bounds pre-pass (PRE_*)
     uint32_t* d_pmask = nullptr;   // per item: PRE_MASK_WORDS words of its word mask
+    uint32_t* d_list = nullptr;    // the items the pre-pass leaves to the tile routine, per XCD
     std::vector<uint32_t> h_codes; // their host copy (upload only on change)
     uint64_t n_bits = 0;
     uint32_t nq = 0;
     uint32_t grid = 0;
-    int win_batch = 7;             // windows per wavefront batch of the persistent kernel (4..7)
+    int win_batch = 6;             // windows per wavefront batch of the persistent kernel (4..7)
+    int prepass = 1;               // bounds pre-pass before the persistent launch
     size_t smem = 0;
     int use_graph = 1;
     hipStream_t cap_stream = nullptr;
@@ -975,6 +977,11 @@ struct ewah_batch {
 
 namespace {
 
+// pre-pass buffers of a batch's launches (null: no pre-pass)
+uint32_t* pre_of(const ewah_batch* b) { return b->prepass ? b->d_pre : nullptr; }
+uint32_t* list_of(const ewah_batch* b) { return b->prepass ? b->d_list : nullptr; }
+constexpr uint32_t PRE_MIN_ITEMS = 65536;   // default: the pre-pass for batches of at least this many items
+
 ewah_status batch_build_graph(ewah_batch* b) {
     if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
@@ -983,7 +990,8 @@ ewah_status batch_build_graph(ewah_batch* b) {
     HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = launch_bump(b->d_work, b->cap_stream);
     hipError_t e2 = launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1,
-                                 g.d_err, b->grid, b->smem, b->cap_stream, nullptr, b->win_batch, b->d_pre, b->d_pmask);
+                                 g.d_err, b->grid, b->smem, b->cap_stream, nullptr, b->win_batch, pre_of(b), b->d_pmask,
+                                 list_of(b));
     hipError_t e3 = hipStreamEndCapture(b->cap_stream, &b->graph);
     HIPCHK(e1);
     HIPCHK(e2);
@@ -1061,6 +1069,7 @@ ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, con
     HIPCHK(hipMemcpy(b->d_qtile, qtile.data(), (nq + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMalloc(&b->d_pre, (size_t)qtile[nq] * 4));
     HIPCHK(hipMalloc(&b->d_pmask, (size_t)qtile[nq] * PRE_MASK_WORDS * 4));
+    HIPCHK(hipMalloc(&b->d_list, (size_t)qtile[nq] * 4));
     HIPCHK(hipMalloc(&b->d_work, WORK_WORDS * 4));
     HIPCHK(hipMemset(b->d_work, 0, WORK_WORDS * 4));
     HIPCHK(hipMalloc(&b->d_codes, 64 * 4));
@@ -1086,6 +1095,7 @@ ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, con
     HIPCHK(hipMalloc(&b->d_qs, nq * sizeof(QueryDev)));
     HIPCHK(hipMemcpy(b->d_qs, b->h_qs.data(), nq * sizeof(QueryDev), hipMemcpyHostToDevice));
     b->smem = tile_smem_bytes(maxN);
+    b->prepass = b->total >= PRE_MIN_ITEMS ? 1 : 0;
     b->grid = (cfg && cfg->grid) ? cfg->grid : g.n_cu * (uint32_t)batch_blocks_per_cu(b->smem);
     b->use_graph = cfg ? cfg->use_graph : 1;
     st = batch_build_graph(b.get());
@@ -1102,7 +1112,7 @@ ewah_status ewah_batch_run(ewah_batch* b, void* hip_stream) {
     } else {
         HIPCHK(launch_bump(b->d_work, s));
         HIPCHK(launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1, g.d_err,
-                            b->grid, b->smem, s, nullptr, b->win_batch, b->d_pre, b->d_pmask));
+                            b->grid, b->smem, s, nullptr, b->win_batch, pre_of(b), b->d_pmask, list_of(b)));
     }
     return EWAH_OK;
 }
@@ -1129,6 +1139,13 @@ ewah_status ewah_batch_set_win_batch(ewah_batch* b, uint32_t win_batch) {
     return batch_build_graph(b);
 }
 
+ewah_status ewah_batch_set_prepass(ewah_batch* b, int on) {
+    if (!b) return fail(EWAH_EINVAL, "null batch");
+    HIPCHK(hipDeviceSynchronize());
+    b->prepass = on ? 1 : 0;
+    return batch_build_graph(b);
+}
+
 void ewah_batch_free(ewah_batch* b) {
     if (!b) return;
     (void)hipDeviceSynchronize();
@@ -1149,6 +1166,7 @@ void ewah_batch_free(ewah_batch* b) {
     if (b->d_itemt) (void)hipFree(b->d_itemt);
     (void)hipFree(b->d_pre);
     (void)hipFree(b->d_pmask);
+    (void)hipFree(b->d_list);
     delete b;
 }
 
@@ -1248,7 +1266,7 @@ ewah_status ewah_batch_time_queries(ewah_batch* b, uint32_t reps, float* busy_us
     for (uint32_t r = 0; r < reps; ++r) {
         HIPCHK(launch_bump(b->d_work, s));
         HIPCHK(launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1, g.d_err,
-                            b->grid, b->smem, s, b->d_itemt, b->win_batch, b->d_pre, b->d_pmask));
+                            b->grid, b->smem, s, b->d_itemt, b->win_batch, pre_of(b), b->d_pmask, list_of(b)));
         HIPCHK(hipMemcpyAsync(ticks.data(), b->d_itemt, 2 * (size_t)b->total * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         for (uint32_t q = 0; q < b->nq; ++q) {

@@ -238,10 +238,13 @@ constexpr int WCAP = 2 * BLOCK;   // cooperative windows listed in LDS per round
 constexpr int MISC_WORDS = 128;   // LDS counters and scratch of the tile routine
 
 // Batched launches: work state of WORK_WORDS words.  work[1] = epoch; the item
-// counter of XCD x at work[WORK_CTR + WORK_STRIDE * x] (one 64-byte line each).
+// counter of XCD x at work[WORK_CTR + WORK_STRIDE * x] (one 64-byte line each); with the
+// bounds pre-pass, the length of XCD x's list of items left to the tile routine at
+// work[WORK_LIST + WORK_STRIDE * x].  Item i belongs to XCD i * NXCD / total.
 constexpr int NXCD = 8;           // XCDs of the MI355X
 constexpr int WORK_CTR = 16, WORK_STRIDE = 16;
-constexpr int WORK_WORDS = WORK_CTR + WORK_STRIDE * NXCD;
+constexpr int WORK_LIST = WORK_CTR + WORK_STRIDE * NXCD;
+constexpr int WORK_WORDS = WORK_LIST + WORK_STRIDE * NXCD;
 constexpr int STAGE_WORDS = TW + 8;   // staged output words per tile (at most TW + 1 are used)
 
 // Bounds pre-pass of a batched launch: per item (query, tile) one result word and a word mask
@@ -284,9 +287,10 @@ hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_
                         size_t smem, hipStream_t s,
                         uint32_t* item_t = nullptr,  // 2 * total words: per-item busy ticks of the tile routine, then
                                                      // of the pre-pass wavefront (null: not timed)
-                        int win_batch = 7,    // windows per wavefront batch: 4..7
+                        int win_batch = 6,    // windows per wavefront batch: 4..7
                         uint32_t* pre = nullptr,     // total words: bounds pre-pass results (null: none)
-                        uint32_t* pmask = nullptr);  // total * PRE_MASK_WORDS words: its word masks
+                        uint32_t* pmask = nullptr,   // total * PRE_MASK_WORDS words: its word masks
+                        uint32_t* list = nullptr);   // total words: the items it leaves, listed per XCD
 hipError_t launch_bump(uint32_t* work, hipStream_t s);   // epoch at work[1], counters cleared
 hipError_t launch_zero_len(uint64_t* out_n, hipStream_t s);
 hipError_t set_smem_limits(size_t max_bytes);

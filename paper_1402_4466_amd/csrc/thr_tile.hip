@@ -1830,7 +1830,8 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_max_kernel(QueryDev q, con
 __global__ __launch_bounds__(256) void thr_bounds_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
                                                           const uint32_t* __restrict__ tq, uint32_t nq, uint32_t total,
                                                           const uint32_t* epoch_ptr, uint32_t* __restrict__ pre,
-                                                          uint32_t* __restrict__ pmask, uint32_t* __restrict__ item_t) {
+                                                          uint32_t* __restrict__ pmask, uint32_t* __restrict__ list,
+                                                          uint32_t* work, uint32_t* __restrict__ item_t) {
     const uint32_t it = blockIdx.x * 4u + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (it >= total) return;
     const uint64_t t0 = item_t ? wall_clock64() : 0ull;
@@ -1839,7 +1840,15 @@ __global__ __launch_bounds__(256) void thr_bounds_kernel(const QueryDev* __restr
     const uint32_t r = pre_bounds(q, it - qtile[qi], *epoch_ptr, pmask + (size_t)it * PRE_MASK_WORDS);
     if (__lane_id() == 0) {
         pre[it] = r;
-        if (item_t) item_t[it] = (uint32_t)(wall_clock64() - t0);
+        if (r != PRE_SETTLED) {   // left to the tile routine: onto its XCD's list
+            const uint32_t x = (uint32_t)((uint64_t)it * NXCD / total);
+            const uint32_t lo = (uint32_t)(((uint64_t)total * x + NXCD - 1) / NXCD);   // first item of XCD x
+            list[lo + atomicAdd(&work[WORK_LIST + WORK_STRIDE * x], 1u)] = it;
+        }
+        if (item_t) {   // ticks of the tile routine (none for a settled tile), then of this wavefront
+            if (r == PRE_SETTLED) item_t[it] = 0u;
+            item_t[total + it] = (uint32_t)(wall_clock64() - t0);
+        }
     }
 }
 
@@ -1849,48 +1858,54 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __r
                                                           const BitmapDev* __restrict__ table,
                                                           uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err,
                                                           uint32_t* __restrict__ item_t, const uint32_t* __restrict__ pre,
-                                                          const uint32_t* __restrict__ pmask) {
+                                                          const uint32_t* __restrict__ pmask,
+                                                          const uint32_t* __restrict__ list) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t s_item, s_n, s_q[CLAIM_ITEMS], s_pre[CLAIM_ITEMS];
+    __shared__ uint32_t s_n, s_it[CLAIM_ITEMS], s_q[CLAIM_ITEMS], s_pre[CLAIM_ITEMS];
     const uint32_t total = qtile[nq];
     const uint32_t epoch = *epoch_ptr;
     const uint32_t x0 = blockIdx.x % (uint32_t)NXCD;
     while (true) {
-        // wavefront 0 claims a run of up to CLAIM_ITEMS items and reads their queries and
-        // pre-pass results
+        // wavefront 0 claims a run of items and reads their queries and pre-pass results: from
+        // the XCD's list of items the pre-pass left, or (no pre-pass) from the XCD's range of
+        // items; other XCDs' once its own is used up.  Runs are of up to CLAIM_ITEMS items where
+        // an XCD's workgroups have at least 64 runs each to share, else of single items (a short
+        // batch split into long runs would leave workgroups idle).
         if (threadIdx.x < 64) {
-            uint32_t it = total, n = 0;
+            uint32_t c = 0, n = 0, base = 0;
             if (threadIdx.x == 0) {
+                const uint32_t per = (gridDim.x + NXCD - 1) / NXCD;   // workgroups per XCD
                 for (uint32_t d = 0; d < (uint32_t)NXCD; ++d) {
                     const uint32_t x = (x0 + d) % (uint32_t)NXCD;
-                    const uint32_t lo = (uint32_t)((uint64_t)total * x / NXCD);
-                    const uint32_t hi = (uint32_t)((uint64_t)total * (x + 1u) / NXCD);
-                    if (lo == hi) continue;
-                    const uint32_t c = atomicAdd(&work[WORK_CTR + WORK_STRIDE * x], CLAIM_ITEMS);
-                    if (c < hi - lo) { it = lo + c; n = min(CLAIM_ITEMS, hi - lo - c); break; }
+                    const uint32_t lo = (uint32_t)(((uint64_t)total * x + NXCD - 1) / NXCD);
+                    const uint32_t len = list ? __hip_atomic_load(&work[WORK_LIST + WORK_STRIDE * x], __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_AGENT)
+                                              : (uint32_t)(((uint64_t)total * (x + 1u) + NXCD - 1) / NXCD) - lo;
+                    if (len == 0) continue;
+                    const uint32_t k = max(1u, min(CLAIM_ITEMS, len / (64u * per)));
+                    c = atomicAdd(&work[WORK_CTR + WORK_STRIDE * x], k);
+                    if (c < len) { base = lo; n = min(k, len - c); break; }
                 }
             }
-            it = (uint32_t)__builtin_amdgcn_readfirstlane((int)it);
+            c = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
             n = (uint32_t)__builtin_amdgcn_readfirstlane((int)n);
+            base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
             const uint32_t j = threadIdx.x;
             if (j < n) {
-                s_q[j] = nq > 1u ? tq[it + j] : 0u;   // query of the item (a batch of one needs none)
-                s_pre[j] = pre ? pre[it + j] : PRE_NONE;
+                const uint32_t it = list ? list[base + c + j] : base + c + j;
+                s_it[j] = it;
+                s_q[j] = nq > 1u ? tq[it] : 0u;   // query of the item (a batch of one needs none)
+                s_pre[j] = pre ? pre[it] : PRE_NONE;
             }
-            if (j == 0) { s_item = it; s_n = n; }
+            if (j == 0) s_n = n;
         }
         __syncthreads();
         // uniform: the query record is then read into scalar registers
-        const uint32_t it0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_item);
         const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_n);
-        if (it0 >= total) break;
+        if (n == 0) break;
         for (uint32_t j = 0; j < n; ++j) {
-            const uint32_t it = it0 + j;
+            const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_it[j]);
             const uint32_t pj = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pre[j]);
-            if (pj == PRE_SETTLED) {   // done by the pre-pass
-                if (item_t && threadIdx.x == 0) item_t[it] = 0u;
-                continue;
-            }
             const uint32_t qi = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_q[j]);
             const uint64_t t0 = item_t ? wall_clock64() : 0ull;
             QueryDev q = qs[qi];
@@ -1928,7 +1943,10 @@ __global__ void bump_epoch_kernel(uint32_t* work) {
     uint32_t e = work[1] + 1u;
     if ((e & 0xFFFFu) == 0) e += 1u;
     work[1] = e;
-    for (int x = 0; x < NXCD; ++x) work[WORK_CTR + WORK_STRIDE * x] = 0u;
+    for (int x = 0; x < NXCD; ++x) {
+        work[WORK_CTR + WORK_STRIDE * x] = 0u;
+        work[WORK_LIST + WORK_STRIDE * x] = 0u;
+    }
 }
 
 // Output for r = 0 (no words).
@@ -1992,19 +2010,21 @@ hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* tic
 
 hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_t* tq, uint32_t nq, uint32_t total,
                         const BitmapDev* table, uint32_t* work, const uint32_t* epoch_ptr, uint32_t* err, uint32_t grid,
-                        size_t smem, hipStream_t s, uint32_t* item_t, int win_batch, uint32_t* pre, uint32_t* pmask) {
+                        size_t smem, hipStream_t s, uint32_t* item_t, int win_batch, uint32_t* pre, uint32_t* pmask,
+                        uint32_t* list) {
+    if ((pre == nullptr) != (list == nullptr) || (pre && !pmask)) return hipErrorInvalidValue;
     if (pre)
         hipLaunchKernelGGL(thr_bounds_kernel, dim3((total + 3) / 4), dim3(256), 0, s, qs, qtile, tq, nq, total, epoch_ptr,
-                           pre, pmask, item_t ? item_t + total : nullptr);
+                           pre, pmask, list, work, item_t);
     switch (win_batch) {
         case 4: hipLaunchKernelGGL(thr_batch_kernel<4>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
-                                   epoch_ptr, err, item_t, pre, pmask); break;
+                                   epoch_ptr, err, item_t, pre, pmask, list); break;
         case 5: hipLaunchKernelGGL(thr_batch_kernel<5>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
-                                   epoch_ptr, err, item_t, pre, pmask); break;
+                                   epoch_ptr, err, item_t, pre, pmask, list); break;
         case 6: hipLaunchKernelGGL(thr_batch_kernel<6>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
-                                   epoch_ptr, err, item_t, pre, pmask); break;
+                                   epoch_ptr, err, item_t, pre, pmask, list); break;
         case 7: hipLaunchKernelGGL(thr_batch_kernel<7>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
-                                   epoch_ptr, err, item_t, pre, pmask); break;
+                                   epoch_ptr, err, item_t, pre, pmask, list); break;
         default: return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(scan_batch_kernel, dim3(nq), dim3(SCAN_THREADS), 0, s, qs, epoch_ptr, err);

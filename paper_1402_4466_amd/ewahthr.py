@@ -81,6 +81,7 @@ _batch_run = _sig("ewah_batch_run", _i32, [_vp, _vp])
 _batch_set_variants = _sig("ewah_batch_set_variants", _i32, [_vp, _vp])
 _batch_set_grid = _sig("ewah_batch_set_grid", _i32, [_vp, _u32])
 _batch_set_win_batch = _sig("ewah_batch_set_win_batch", _i32, [_vp, _u32])
+_batch_set_prepass = _sig("ewah_batch_set_prepass", _i32, [_vp, _i32])
 _batch_free = _sig("ewah_batch_free", None, [_vp])
 _device_errors = _sig("ewah_device_errors", _i32, [ctypes.POINTER(_u32)])
 _num_cus = _sig("ewah_num_cus", _u32, [])
@@ -121,7 +122,8 @@ EXPORTED = ["ewah_init", "ewah_last_error", "ewah_register", "ewah_register_many
             "ewah_get_stats", "ewah_device_words", "ewah_output_bound", "ewah_threshold", "ewah_threshold_v", "ewah_threshold_noalloc",
             "ewah_symmetric", "ewah_opt_threshold", "ewah_count_histogram",
             "ewah_variant_code", "ewah_variant_code_ex", "ewah_default_variant", "ewah_batch_plan", "ewah_batch_run",
-            "ewah_batch_set_variants", "ewah_batch_set_grid", "ewah_batch_set_win_batch", "ewah_batch_free", "ewah_device_errors",
+            "ewah_batch_set_variants", "ewah_batch_set_grid", "ewah_batch_set_win_batch", "ewah_batch_set_prepass",
+            "ewah_batch_free", "ewah_device_errors",
             "ewah_num_cus", "ewah_query_features", "ewah_batch_features", "ewah_batch_select",
             "ewah_batch_get_variants", "ewah_batch_time_queries", "ewah_batch_select_model",
             "ewah_variant_code_full", "ewah_selector_load", "ewah_selector_save", "ewah_selector_free",
@@ -320,7 +322,8 @@ class Batch:
         self._h = h
         self.nq = nq
         self.grid = grid          # 0: the library default (as many workgroups as are resident at once)
-        self.win_batch = 7
+        self.win_batch = 6
+        self.prepass = None       # None: the library default (on for batches of at least 65,536 items)
 
     def run(self, stream=None):
         _check(_batch_run(self._h, _stream_ptr(stream)), "batch_run")
@@ -337,6 +340,10 @@ class Batch:
     def set_win_batch(self, win_batch: int):
         _check(_batch_set_win_batch(self._h, win_batch), "batch_set_win_batch")
         self.win_batch = win_batch
+
+    def set_prepass(self, on: bool):
+        _check(_batch_set_prepass(self._h, 1 if on else 0), "batch_set_prepass")
+        self.prepass = bool(on)
 
     def features(self, feat_ptr: int, stream=None):
         _check(_batch_features(self._h, feat_ptr, _stream_ptr(stream)), "batch_features")

@@ -41,7 +41,7 @@ class PooledBatch:
             grid = int(self.tuned["grid"]) if self.tuned else 2 * E.num_cus()
         self.batch.set_grid(grid)
         if self.tuned:
-            self.batch.set_win_batch(int(self.tuned.get("win_batch", 7)))
+            self.batch.set_win_batch(int(self.tuned.get("win_batch", 6)))
         self.grid = grid
         self.signature = signature
 

@@ -57,11 +57,12 @@ def test_batched_trivial_thresholds_and_single_inputs(G):
     wants = [O.threshold([pool[i] for i in idx], n_bits, T, want_hist=False)[0] for idx, T in qs]
     batch = E.Batch(bms, qs, [o.data_ptr() for o in outs], caps, [n.data_ptr() for n in ns], use_graph=True)
     try:
-        for v, wb in [(c, w) for c in codes for w in (4, 5, 6, 7)]:
+        for v, wb, pre in [(c, w, p) for c in codes for w in (4, 5, 6, 7) for p in (False, True)]:
             batch.set_variants(np.full(len(qs), v, dtype=np.uint32))
             batch.set_win_batch(wb)
+            batch.set_prepass(pre)
             for rep in range(2):
-                _say(f"batched edges: variant {v:#x}, {wb} windows per batch, replay {rep}")
+                _say(f"batched edges: variant {v:#x}, {wb} windows per batch, pre-pass {pre}, replay {rep}")
                 for o in outs:
                     o.fill_(-1)
                 batch.run()
@@ -69,7 +70,7 @@ def test_batched_trivial_thresholds_and_single_inputs(G):
                 assert E.device_errors() == 0
                 for i, (idx, T) in enumerate(qs):
                     got = G.fetch(outs[i], ns[i])
-                    assert np.array_equal(got, wants[i]), (v, rep, i, len(idx), T)
+                    assert np.array_equal(got, wants[i]), (v, pre, rep, i, len(idx), T)
     finally:
         batch.free()
         for b in bms:
@@ -142,14 +143,17 @@ def test_eight_row_bounds_settle_what_quarters_cannot(G):
                 outs.append(o); ns.append(n); caps.append(c)
             batch = E.Batch(bms, qs, [o.data_ptr() for o in outs], caps, [n.data_ptr() for n in ns], use_graph=True)
             try:
-                for v in codes:
+                for v, pre in [(c, p) for c in codes for p in (False, True)]:
                     batch.set_variants(np.full(len(qs), v, dtype=np.uint32))
-                    _say(f"8-row bounds: T={T}, variant {v:#x}")
+                    batch.set_prepass(pre)
+                    _say(f"8-row bounds: T={T}, variant {v:#x}, pre-pass {pre}")
+                    for o in outs:
+                        o.fill_(-1)
                     batch.run()
                     torch.cuda.synchronize()
                     assert E.device_errors() == 0
                     for i, (idx, t) in enumerate(qs):
-                        assert np.array_equal(G.fetch(outs[i], ns[i]), wants[i]), ("batched", T, v, i)
+                        assert np.array_equal(G.fetch(outs[i], ns[i]), wants[i]), ("batched", T, v, pre, i)
             finally:
                 batch.free()
     finally:

@@ -8,6 +8,7 @@
 * Batches with fewer (query, tile) items than XCD ranges, and grids of one and
   three workgroups, so that ranges are empty and every item is taken from
   another range.
+* Every batch with the bounds pre-pass and without it.
 """
 import os
 import re
@@ -33,7 +34,7 @@ def G():
     return gpu_util
 
 
-def _run_batch(E, G, bms, pool, n_bits, queries, grid=0, use_graph=True):
+def _run_batch(E, G, bms, pool, n_bits, queries, grid=0, use_graph=True, prepass=None):
     import torch
     outs, ns, caps = [], [], []
     for idx, _ in queries:
@@ -41,6 +42,8 @@ def _run_batch(E, G, bms, pool, n_bits, queries, grid=0, use_graph=True):
         outs.append(o); ns.append(n); caps.append(c)
     batch = E.Batch(bms, queries, [o.data_ptr() for o in outs], caps, [n.data_ptr() for n in ns],
                     grid=grid, use_graph=use_graph)
+    if prepass is not None:
+        batch.set_prepass(prepass)
     batch.run()
     torch.cuda.synchronize()
     got = [G.fetch(outs[i], ns[i]) for i in range(len(queries))]
@@ -68,9 +71,10 @@ def test_bounds_around_granularity_switch(G):
         for (idx, T), want in zip(queries, wants):
             got = G.gpu_threshold([bms[i] for i in idx], T)
             assert np.array_equal(got, want), (len(idx), T)
-        got = _run_batch(E, G, bms, pool, n_bits, queries)
-        for i, want in enumerate(wants):
-            assert np.array_equal(got[i], want), ("batched", len(queries[i][0]), queries[i][1])
+        for pre in (False, True):
+            got = _run_batch(E, G, bms, pool, n_bits, queries, prepass=pre)
+            for i, want in enumerate(wants):
+                assert np.array_equal(got[i], want), ("batched", pre, len(queries[i][0]), queries[i][1])
     finally:
         for b in bms:
             b.release()
@@ -89,10 +93,10 @@ def test_small_batches_and_grids(G):
             qs = D.queries(606 + nq, nq, n, 1, n)
             queries = [(q.idx, q.T) for q in qs]
             wants = [O.threshold([pool[i] for i in idx], n_bits, T, want_hist=False)[0] for idx, T in queries]
-            for grid in (0, 1, 3):
-                got = _run_batch(E, G, bms, pool, n_bits, queries, grid=grid, use_graph=(grid != 3))
+            for grid, pre in [(g, p) for g in (0, 1, 3) for p in (False, True)]:
+                got = _run_batch(E, G, bms, pool, n_bits, queries, grid=grid, use_graph=(grid != 3), prepass=pre)
                 for i, want in enumerate(wants):
-                    assert np.array_equal(got[i], want), (n_bits, nq, grid, i)
+                    assert np.array_equal(got[i], want), (n_bits, nq, grid, pre, i)
         finally:
             for b in bms:
                 b.release()

@@ -221,17 +221,19 @@ def test_batched_matches_plain_and_oracle(G):
     batch = E.Batch(bms, [(q.idx, q.T) for q in qs], [o.data_ptr() for o in outs], caps,
                     [n.data_ptr() for n in ns], variants=variants, use_graph=True)
     wants = [O.threshold([pool[i] for i in q.idx], n_bits, q.T, want_hist=False)[0] for q in qs]
-    for rep in range(3):
-        for o in outs:
-            o.zero_()
-        batch.run()
-        torch.cuda.synchronize()
-        x = torch.ones(1000, device="cuda").sum()   # eager work between replays
-        torch.cuda.synchronize()
-        assert E.device_errors() == 0
-        for i, q in enumerate(qs):
-            got = G.fetch(outs[i], ns[i])
-            assert np.array_equal(got, wants[i]), (rep, i)
+    for pre in (False, True):   # without and with the bounds pre-pass
+        batch.set_prepass(pre)
+        for rep in range(3):
+            for o in outs:
+                o.zero_()
+            batch.run()
+            torch.cuda.synchronize()
+            x = torch.ones(1000, device="cuda").sum()   # eager work between replays
+            torch.cuda.synchronize()
+            assert E.device_errors() == 0
+            for i, q in enumerate(qs):
+                got = G.fetch(outs[i], ns[i])
+                assert np.array_equal(got, wants[i]), (pre, rep, i)
     # eager (no graph) and grid change
     batch.set_grid(7)
     batch.run()
