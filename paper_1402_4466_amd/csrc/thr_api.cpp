@@ -1252,7 +1252,10 @@ ewah_status ewah_batch_select_model(ewah_batch* b, const ewah_selector* sel, int
 ewah_status ewah_batch_time_queries(ewah_batch* b, uint32_t reps, float* busy_us, void* hip_stream) {
     if (!b || !busy_us || reps == 0) return fail(EWAH_EINVAL, "bad arguments");
     hipStream_t s = (hipStream_t)hip_stream;
-    if (!b->d_itemt) HIPCHK(hipMalloc(&b->d_itemt, std::max<size_t>(2 * (size_t)b->total, 1) * 4));
+    if (!b->d_itemt) {
+        HIPCHK(hipMalloc(&b->d_itemt, std::max<size_t>(2 * (size_t)b->total, 1) * 4));
+        HIPCHK(hipMemset(b->d_itemt, 0, std::max<size_t>(2 * (size_t)b->total, 1) * 4));
+    }
     int khz = 0;
     HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g.device));
     if (khz <= 0) return fail(EWAH_EDEVICE, "device reports no wall-clock rate");
@@ -1261,8 +1264,8 @@ ewah_status ewah_batch_time_queries(ewah_batch* b, uint32_t reps, float* busy_us
     std::vector<uint32_t> ticks(2 * (size_t)b->total);
     std::vector<double> best(b->nq, 1e300);
     // a pre-pass wavefront holds 1 / pre_waves_per_cu of a CU, a workgroup of the tile routine
-    // 1 / batch_blocks_per_cu: its ticks count at that ratio
-    const double wpre = (double)batch_blocks_per_cu(b->smem) / (double)pre_waves_per_cu();
+    // 1 / batch_blocks_per_cu: its ticks count at that ratio (none without the pre-pass)
+    const double wpre = b->prepass ? (double)batch_blocks_per_cu(b->smem) / (double)pre_waves_per_cu() : 0.0;
     for (uint32_t r = 0; r < reps; ++r) {
         HIPCHK(launch_bump(b->d_work, s));
         HIPCHK(launch_batch(b->d_qs, b->d_qtile, b->d_tq, b->nq, b->total, g.d_table, b->d_work, b->d_work + 1, g.d_err,

@@ -159,3 +159,32 @@ def test_eight_row_bounds_settle_what_quarters_cannot(G):
     finally:
         for b in bms:
             b.release()
+
+
+def test_query_busy_times_with_and_without_prepass(G):
+    """Per-query busy times (the selector's labels) of one batch with the bounds pre-pass off,
+    on, and off again: every time is positive and of the order of the batch's own launch, so
+    the pre-pass share is counted only when the pre-pass ran."""
+    E = G.lib()
+    n_bits = 4 * 512 * 64 + 77
+    pool_n = 32
+    d = D.pool_densities(pool_n, seed=5150)
+    pool = D.bitmaps(D.IID, d, 0.0, n_bits, [D.key(5150, k) for k in range(pool_n)])
+    bms = E.register_many(pool, n_bits)
+    qs = [(q.idx, q.T) for q in D.queries(5151, 24, pool_n, 2, pool_n)]
+    outs, ns, caps = [], [], []
+    for idx, _ in qs:
+        o, n, c = G.alloc_out(n_bits, int(sum(len(pool[i]) for i in idx)))
+        outs.append(o); ns.append(n); caps.append(c)
+    batch = E.Batch(bms, qs, [o.data_ptr() for o in outs], caps, [n.data_ptr() for n in ns], use_graph=False)
+    try:
+        for pre in (False, True, False):
+            batch.set_prepass(pre)
+            t = batch.time_queries(2)
+            _say(f"busy times, pre-pass {pre}: max {t.max():.1f} us")
+            assert np.all(np.isfinite(t)) and np.all(t > 0) and np.all(t < 1e5), (pre, t)
+        assert E.device_errors() == 0
+    finally:
+        batch.free()
+        for b in bms:
+            b.release()
