@@ -1832,7 +1832,11 @@ __global__ __launch_bounds__(256) void thr_bounds_kernel(const QueryDev* __restr
                                                           const uint32_t* epoch_ptr, uint32_t* __restrict__ pre,
                                                           uint32_t* __restrict__ pmask, uint32_t* __restrict__ list,
                                                           uint32_t* work, uint32_t* __restrict__ item_t) {
-    const uint32_t it = blockIdx.x * 4u + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    // workgroup b runs on XCD b % NXCD: each XCD takes a contiguous share of the items, so the
+    // tiles of a query that share its descriptors and quarter-count lines meet in one L2
+    const uint32_t nwg = gridDim.x, x = blockIdx.x % (uint32_t)NXCD;
+    const uint32_t wg = x * (nwg / NXCD) + min(x, nwg % NXCD) + blockIdx.x / (uint32_t)NXCD;
+    const uint32_t it = wg * 4u + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (it >= total) return;
     const uint64_t t0 = item_t ? wall_clock64() : 0ull;
     const uint32_t qi = nq > 1u ? tq[it] : 0u;
