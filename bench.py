@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
-STREAM_CEILING_GBS = 6800.0   # measured: sequential 512-byte wavefront reads over 4 GiB
+STREAM_CEILING_GBS = 6635.0   # measured: sequential 512-byte wavefront reads over 4 GiB (profiles/stream_ceiling.md)
 
 
 def log(*a):
