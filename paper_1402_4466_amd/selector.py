@@ -37,8 +37,8 @@ N_FEATURES = 16
 #             Section 6.2); taken when T <= bit length of N, else as sparse_*;
 #   *_gate*   the per-group count bounds (RBMrg's second case, Section 6.4, inside a
 #             tile) counted always, never, or above 1.5x the mean bound instead of
-#             above 1.1x (also combined with the long walks and the all-cooperative
-#             decode).
+#             above 1.1x (also combined with the long walks, the all-cooperative
+#             decode and the unary counter).
 ARMS = [
     ("hybrid_w8", True, 8, 8, False, 0),
     ("sparse_w8", False, 8, 8, False, 0),
@@ -54,6 +54,8 @@ ARMS = [
     ("hybrid_walk128_gate_always", True, 128, 255, False, 1),
     ("sparse_walk64_gate_always", False, 64, 64, False, 1),
     ("hybrid_coop_gate_always", True, 0, 0, False, 1),
+    ("looped_coop_gate_1.5", False, 0, 0, True, 3),
+    ("hybrid_coop_gate_1.5", True, 0, 0, False, 3),
 ]
 
 
