@@ -242,7 +242,8 @@ typedef struct {
 
 typedef struct {
     uint32_t grid;          /* persistent workgroups, 0 = all that can be resident at once */
-    int use_graph;          /* 1 = capture bump + persistent kernel into a hipGraph */
+    int use_graph;          /* 1 = capture the batch's launches (bump, bounds pre-pass, persistent
+                               kernel, scan, placement) into a hipGraph */
 } ewah_batch_config;
 
 typedef struct ewah_batch ewah_batch;
@@ -253,8 +254,10 @@ typedef struct ewah_batch ewah_batch;
  * each query with the meaning of ewah_threshold (Section 2).
  * Plans a batch: uploads the query table (inputs as pool indices, thresholds,
  * output pointers, variants) and, with use_graph, captures the launch into a
- * HIP graph.  pool[] must stay registered while the batch exists.  All pool
- * bitmaps must have the same n_bits > 0.  Synchronous.
+ * HIP graph.  Device memory per (query, tile) item: a 64-byte tile state, a
+ * staging area of 520 words and 72 bytes of bounds pre-pass results.  pool[] must
+ * stay registered while the batch exists.  All pool bitmaps must have the same
+ * n_bits > 0.  Synchronous.
  */
 ewah_status ewah_batch_plan(const ewah_bitmap* const* pool, uint32_t pool_n, const ewah_query* q, uint32_t nq,
                             const ewah_batch_config* cfg, ewah_batch** out);
