@@ -125,8 +125,7 @@ struct Built {
     std::vector<uint4> loc;    // per tile boundary: covering marker index, its run start, the marker word
     std::vector<uint4> desc;   // per CHUNK words: marker mask (lo, hi), position of the chunk's first word
     std::vector<uint4> pres;   // per tile PV_COARSE records: 4-word groups holding a dirty word or a one-fill
-    std::vector<uint32_t> presq;   // per tile PQ_WORDS words: quarter-word groups holding a one, 8-row groups
-                                   // holding a one
+    std::vector<uint32_t> presq;   // pq_words(tiles) words: per-word, quarter-word and 8-row groups holding a one
     std::vector<uint16_t> qcnt;    // per tile: number of quarter-word groups holding a one
     ewah_stats st{};
 };
@@ -226,32 +225,34 @@ ewah_status build_index(const uint64_t* w, uint64_t nw, uint64_t n_bits, Built& 
     if (u != U) return fail(EWAH_EFORMAT, "stream covers " + std::to_string(u) + " words, expected " + std::to_string(U));
     if (tiles) b.loc[tiles] = make_uint4((uint32_t)nw, (uint32_t)U, 0, 0);
     // per tile: the quarter bits and their count, and the word bits ORed over each group of 4 words
-    b.presq.assign(tiles * PQ_WORDS, 0u);
+    b.presq.assign(pq_words((uint32_t)tiles), 0u);
     b.qcnt.assign(tiles, 0u);
     b.pres.assign(tiles * PV_COARSE, make_uint4(0, 0, 0, 0));
     static_assert(NQ_TILE < 65536, "quarter counts fit 16 bits");
     static_assert(TW % 64 == 0 && GW_COARSE == 4, "presence record packing");
     for (uint64_t t = 0; t < tiles; ++t) {
         const uint64_t* qw = qbits.data() + t * (NQ_TILE / 64);
-        uint32_t* rec = b.presq.data() + t * PQ_WORDS;
+        uint32_t* wrec = b.presq.data() + t * PQ_W_TILE;
+        uint32_t* qrec = b.presq.data() + pq_quarters((uint32_t)tiles) + t * PQ_Q_TILE;
         uint32_t nq = 0;
         for (int k = 0; k < NQ_TILE / 64; ++k) {
-            rec[2 * k] = (uint32_t)qw[k];
-            rec[2 * k + 1] = (uint32_t)(qw[k] >> 32);
+            qrec[2 * k] = (uint32_t)qw[k];
+            qrec[2 * k + 1] = (uint32_t)(qw[k] >> 32);
             nq += (uint32_t)popc64(qw[k]);
         }
         b.qcnt[t] = (uint16_t)nq;
         const uint64_t* ow = obits.data() + t * (NO_TILE / 64);
-        // the 32 bits of words 4 m .. 4 m + 3 (m = 2 l + h) go to record word PQ_OCT + 64 h + l:
-        // the halves of the words of lanes l = 0 .. 63 each lie together
+        // the 32 bits of words 4 m .. 4 m + 3 (m = 2 l + h) go to word l of half h: the halves of
+        // the words of lanes l = 0 .. 63 each lie together
         for (int k = 0; k < NO_TILE / 64; ++k) {
             for (int e = 0; e < 2; ++e) {
                 const int m = 2 * k + e;
-                rec[PQ_OCT + 64 * (m % 2) + m / 2] = (uint32_t)(ow[k] >> (32 * e));
+                b.presq[pq_octets((uint32_t)tiles, (uint32_t)(m % 2)) + t * PQ_O_TILE + m / 2] =
+                    (uint32_t)(ow[k] >> (32 * e));
             }
         }
         for (int wd = 0; wd < TW; ++wd)   // a word holds a one iff one of its quarters does
-            if ((qw[wd / 16] >> (4 * (wd % 16))) & 15ull) rec[PQ_WB + wd / 32] |= 1u << (wd % 32);
+            if ((qw[wd / 16] >> (4 * (wd % 16))) & 15ull) wrec[wd / 32] |= 1u << (wd % 32);
         const uint64_t* w = gbits.data() + t * (TW / 64);
         uint32_t c[4 * PV_COARSE] = {};
         for (int k = 0; k < TW / 64; ++k) {

@@ -68,11 +68,22 @@ constexpr int PV_COARSE = NG_COARSE / 128;   // 16-byte 4-word-group records per
 constexpr int PMW_MAX = NG_FINE / 32;         // 32-bit words of the largest group mask
 constexpr int NQ_TILE = 4 * TW;               // quarter-word groups per tile
 constexpr int NO_TILE = 8 * TW;               // 8-row groups per tile
-constexpr int PQ_OCT = NQ_TILE / 32;          // record word where the 8-row bits start
-constexpr int PQ_WB = PQ_OCT + NO_TILE / 32;  // record word where the per-word bits start
-constexpr int PQ_WORDS = PQ_WB + TW / 32 + 16;   // 32-bit words per tile and bitmap (a multiple of 32:
-                                                 // every record and part of one starts on a 128-byte line)
-static_assert(PQ_WORDS % 32 == 0 && PQ_OCT % 32 == 0 && PQ_WB % 16 == 0, "record alignment");
+// Fine presence records of a bitmap of `tiles` tiles: four arrays side by side, each holding the
+// tiles in order, so that neighbouring tiles' parts lie next to each other:
+//   per-word bits, PQ_W_TILE words per tile from word 0 (bit w: word w of the tile holds a one);
+//   quarter bits, PQ_Q_TILE words per tile from pq_quarters(tiles) (bit 4w + j: rows
+//   [16j, 16j + 16) of word w hold a one);
+//   8-row bits of half h = 0, 1, PQ_O_TILE words per tile from pq_octets(tiles, h) (word l,
+//   bit 8i + j: rows [8j, 8j + 8) of word 8l + 4h + i hold a one).
+constexpr uint32_t PQ_W_TILE = TW / 32;
+constexpr uint32_t PQ_Q_TILE = NQ_TILE / 32;
+constexpr uint32_t PQ_O_TILE = NO_TILE / 64;
+__host__ __device__ inline uint32_t pq_quarters(uint32_t tiles) { return (tiles * PQ_W_TILE + 31u) & ~31u; }
+__host__ __device__ inline uint32_t pq_octets(uint32_t tiles, uint32_t h) {
+    return pq_quarters(tiles) + tiles * PQ_Q_TILE + h * tiles * PQ_O_TILE;
+}
+__host__ __device__ inline uint32_t pq_words(uint32_t tiles) { return pq_octets(tiles, 2u); }
+static_assert(PQ_Q_TILE % 32 == 0 && PQ_O_TILE % 32 == 0, "quarter and 8-row parts on 128-byte lines");
 static_assert(TW % 512 == 0 && NG_FINE <= BLOCK, "presence groups per tile");
 constexpr int CHUNK = 64;         // compressed words per skip-index entry (one wavefront)
 constexpr int MAXP = 12;          // bit planes: inputs per query < 2^12 (LDS budget)
@@ -90,11 +101,9 @@ struct BitmapDev {
     uint32_t U;              // uncompressed words
     const uint4* pres;       // per tile PV_COARSE records: bit g set iff words [4g, 4g + 4) of the
                              // tile hold a dirty word or a one-fill (the input can contribute there)
-    const uint32_t* presq;   // per tile PQ_WORDS words: in words 0 .. NQ_TILE / 32 - 1, bit 4w + j set
-                             // iff rows [16j, 16j + 16) of word w of the tile hold a one (a one-fill,
-                             // or a nonzero quarter of a dirty word); in word PQ_OCT + 64h + l, bit
-                             // 8i + j set iff rows [8j, 8j + 8) of word 8l + 4h + i hold a one; from
-                             // word PQ_WB, bit w set iff word w holds a one; the rest is padding
+    const uint32_t* presq;   // fine presence records, pq_words(tiles) words (layout at pq_quarters):
+                             // a word, quarter or 8-row group holds a one where a one-fill covers it
+                             // or a dirty word has a nonzero bit there
     const uint16_t* qcnt;    // per tile: how many quarter-word groups of the tile hold a one (the
                              // tiles of a bitmap side by side, so neighbouring tiles share lines)
 };

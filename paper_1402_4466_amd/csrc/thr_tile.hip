@@ -575,8 +575,8 @@ __device__ __forceinline__ void count_quads(const uint32_t* prs, uint32_t pcap, 
 }
 
 // Per-group bounds of a tile of a query of at most PCAP_FINE inputs, from its presence
-// records (qptr[k]: the tile's record of input k, in LDS).  One pass: lane l of wavefront w
-// adds record word off + l of inputs w, w + 8, ... (32 groups; lanes with skip set read
+// records (qptr[k]: input k's records, in LDS).  One pass: lane l of wavefront w adds record
+// word off (the tile's part for lane l) of inputs w, w + 8, ... (32 groups; lanes with skip set read
 // nothing and add zeros), eight records at a time through a carry-save-adder tree, into a
 // bit-sliced counter of QP planes; the eight wavefronts' counters are summed through LDS
 // (part: 7 * QP * 64 words) in three rounds, and wavefront 0 gets the groups whose sum is
@@ -678,20 +678,21 @@ __device__ __forceinline__ uint32_t bound_pass(const uint32_t* const* qptr, uint
 // play, the words still in play are bounded again from the 8-row records, which settles most
 // of the tiles the quarters leave almost settled.  All threads must call.
 __device__ __forceinline__ void fine_bounds(const uint32_t* const* qptr, uint32_t N, uint32_t tz, uint32_t nPos,
-                                            uint32_t* part, uint32_t* pmw, uint32_t* flag) {
+                                            uint32_t t, uint32_t tiles, uint32_t* part, uint32_t* pmw, uint32_t* flag) {
     const int lane = __lane_id();
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t w0 = 8u * (uint32_t)lane;
     const uint32_t vmask = (1u << (nPos > w0 ? min(nPos - w0, 8u) : 0u)) - 1u;   // words of this lane in the tile
     // pass 0: quarters (lane l holds quarters 32l .. 32l + 31, four per word); passes 1 and 2:
-    // the 8-row groups of words w0 + 4h .. w0 + 4h + 3 (h = pass - 1), record word PQ_OCT + 64h + l,
-    // where some of those words are still in play
+    // the 8-row groups of words w0 + 4h .. w0 + 4h + 3 (h = pass - 1), word l of half h of the
+    // tile's 8-row bits, where some of those words are still in play
     uint32_t w8 = 0;
 #pragma unroll 1
     for (uint32_t pass = 0; pass < 3; ++pass) {
         const uint32_t h = pass > 0 ? pass - 1u : 0u;
         const bool skip = pass > 0 && ((w8 | ~vmask) >> (4 * h) & 15u) == 15u;
-        const uint32_t off = pass == 0 ? (uint32_t)lane : (uint32_t)PQ_OCT + 64u * h + (uint32_t)lane;
+        const uint32_t off = (pass == 0 ? pq_quarters(tiles) + t * PQ_Q_TILE : pq_octets(tiles, h) + t * PQ_O_TILE) +
+                             (uint32_t)lane;
         const uint32_t lt = bound_pass(qptr, N, off, skip, tz, part);
         if (pass == 0) {
             uint32_t m = lt & (lt >> 1);
@@ -818,7 +819,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
                 const BitmapDev B = input_of(q, table, k);
                 // the presence count or record and both locator entries are loaded before
                 // any is used, so the classify step waits for memory once
-                const uint32_t* qr = B.presq + (size_t)t * PQ_WORDS;
+                const uint32_t* qr = B.presq;   // the tile's parts are found from t in the bounds step
                 uint4 pr = make_uint4(0u, 0u, 0u, 0u);
                 uint32_t qc = 0;
                 static_assert(PV_COARSE == 1, "one 4-word-group record per tile");
@@ -914,7 +915,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
         pm.on = pre == PRE_MASK;   // bounds of the pre-pass (a tile it settled never gets here)
     } else if (mode == 0 && misc[M_DFULL] < Tz && gate != GATE_NEVER &&
                (gate == GATE_ALWAYS || 10ull * Tz * nfull > gnum * misc[M_PSUM])) {
-        if (fine) fine_bounds(qptr, N, Tz, nPos, prs, misc + M_PR, misc + M_TMP);
+        if (fine) fine_bounds(qptr, N, Tz, nPos, t, tiles, prs, misc + M_PR, misc + M_TMP);
         else count_quads<16>(prs, PCAP_COARSE, min(N, PCAP_COARSE), gcnt);
         if (N > pcap) {   // the rest of very wide queries (4-word groups): wavefront ballots
             __syncthreads();
@@ -1454,7 +1455,7 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
 
 // ------------------------------------------------------------ bounds pre-pass
 
-// Adds, for every input k < N of a query, word off of its presence record of the tile into the
+// Adds, for every input k < N of a query, word off of its presence records into the
 // bit-sliced counter c (one wavefront; lane 64 r + i of round r holds input k's record at rp[r];
 // lanes with skip set load nothing).  32 loads are in flight before any is added.
 __device__ __forceinline__ void count_records(const uint32_t* const* rp, uint32_t N, uint32_t off, bool skip,
@@ -1510,7 +1511,7 @@ __device__ uint32_t pre_bounds(const QueryDev& q, uint32_t t, uint32_t epoch, ui
         rp[r] = nullptr;
         cp[r] = nullptr;
         if (k < N) {
-            rp[r] = gp(q.bms)[k].presq + (size_t)t * PQ_WORDS;
+            rp[r] = gp(q.bms)[k].presq;
             cp[r] = gp(q.bms)[k].qcnt + t;
         }
     }
@@ -1536,22 +1537,23 @@ __device__ uint32_t pre_bounds(const QueryDev& q, uint32_t t, uint32_t epoch, ui
         // the gate of the tile routine: bounds only where they are likely to prune
         if (dfull >= T || gate == GATE_NEVER || (gate != GATE_ALWAYS && 10ull * T * nfull <= gnum * psum))
             return PRE_OPEN;
-        // lane l takes words 8 l .. 8 l + 7: first whole words (its byte of record word
-        // PQ_WB + l / 4), then the quarters of the words still in play (record word l: quarters
-        // 32 l .. 32 l + 31, four per word), then their 8-row groups (record word
-        // PQ_OCT + 64 h + l: words 8 l + 4 h .. 8 l + 4 h + 3)
+        // lane l takes words 8 l .. 8 l + 7: first whole words (its byte of the tile's per-word
+        // bits word l / 4), then the quarters of the words still in play (the tile's quarter word
+        // l: quarters 32 l .. 32 l + 31, four per word), then their 8-row groups (word l of half h
+        // of the tile's 8-row bits: words 8 l + 4 h .. 8 l + 4 h + 3)
         const uint32_t w0 = 8u * (uint32_t)lane;
         vmask = (1u << (nPos > w0 ? min(nPos - w0, 8u) : 0u)) - 1u;   // words of this lane in the tile
         uint32_t c[QP];
 #pragma unroll
         for (int p = 0; p < QP; ++p) c[p] = 0u;
-        count_records(rp, N, (uint32_t)PQ_WB + ((uint32_t)lane >> 2), false, c);
+        const uint32_t tiles = q.tiles;
+        count_records(rp, N, t * PQ_W_TILE + ((uint32_t)lane >> 2), false, c);
         w8 = (below(c, T) >> (8u * ((uint32_t)lane & 3u))) & vmask;
         if (__ballot(w8 != vmask) != 0ull) {
             const bool skip = (w8 | ~vmask | ~0xFFu) == ~0u;
 #pragma unroll
             for (int p = 0; p < QP; ++p) c[p] = 0u;
-            count_records(rp, N, (uint32_t)lane, skip, c);
+            count_records(rp, N, pq_quarters(tiles) + t * PQ_Q_TILE + (uint32_t)lane, skip, c);
             uint32_t m = below(c, T);
             m &= m >> 1;
             m &= m >> 2;   // bit 4 i: all four quarters of word w0 + i
@@ -1565,7 +1567,7 @@ __device__ uint32_t pre_bounds(const QueryDev& q, uint32_t t, uint32_t epoch, ui
             if (__ballot(!skip) == 0ull) continue;
 #pragma unroll
             for (int p = 0; p < QP; ++p) c[p] = 0u;
-            count_records(rp, N, (uint32_t)PQ_OCT + 64u * h + (uint32_t)lane, skip, c);
+            count_records(rp, N, pq_octets(tiles, h) + t * PQ_O_TILE + (uint32_t)lane, skip, c);
             uint32_t o = below(c, T);
             o &= o >> 1;
             o &= o >> 2;
