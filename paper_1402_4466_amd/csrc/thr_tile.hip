@@ -1457,7 +1457,8 @@ __device__ void process_tile(const QueryDev& q, const BitmapDev* __restrict__ ta
 
 // Adds, for every input k < N of a query, word off of its presence records into the
 // bit-sliced counter c (one wavefront; lane 64 r + i of round r holds input k's record at rp[r];
-// lanes with skip set load nothing).  32 loads are in flight before any is added.
+// lanes with skip set load nothing).  16 loads are in flight before any is added (a smaller
+// batch keeps the pass at 62 VGPRs, 8 wavefronts per SIMD).
 __device__ __forceinline__ void count_records(const uint32_t* const* rp, uint32_t N, uint32_t off, bool skip,
                                               uint32_t* c) {
 #pragma unroll
@@ -1466,11 +1467,11 @@ __device__ __forceinline__ void count_records(const uint32_t* const* rp, uint32_
         const uint64_t base = (uint64_t)(uintptr_t)rp[r];
         const int blo = (int)(uint32_t)base, bhi = (int)(uint32_t)(base >> 32);
 #pragma unroll 1
-        for (uint32_t j0 = 0; j0 < 64u && 64u * (uint32_t)r + j0 < N; j0 += 32u) {
-            const uint32_t ni = min(32u, N - 64u * (uint32_t)r - j0);
-            uint32_t x[32];
+        for (uint32_t j0 = 0; j0 < 64u && 64u * (uint32_t)r + j0 < N; j0 += 16u) {
+            const uint32_t ni = min(16u, N - 64u * (uint32_t)r - j0);
+            uint32_t x[16];
 #pragma unroll
-            for (int i = 0; i < 32; ++i) {
+            for (int i = 0; i < 16; ++i) {
                 x[i] = 0u;
                 if ((uint32_t)i < ni && !skip) {
                     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(blo, (int)j0 + i);
@@ -1479,7 +1480,7 @@ __device__ __forceinline__ void count_records(const uint32_t* const* rp, uint32_
                 }
             }
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
+            for (int g = 0; g < 2; ++g) {
                 if ((uint32_t)(8 * g) >= ni) break;
                 add8(c, x + 8 * g);
             }
