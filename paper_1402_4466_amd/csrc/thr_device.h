@@ -248,8 +248,9 @@ constexpr int MISC_WORDS = 128;   // LDS counters and scratch of the tile routin
 
 // Batched launches: work state of WORK_WORDS words.  work[1] = epoch; the item
 // counter of XCD x at work[WORK_CTR + WORK_STRIDE * x] (one 64-byte line each); with the
-// bounds pre-pass, the length of XCD x's list of items left to the tile routine at
-// work[WORK_LIST + WORK_STRIDE * x].  Item i belongs to XCD i * NXCD / total.
+// bounds pre-pass, the lengths of the front part (items of queries of at least 128 inputs) and
+// the back part (the others) of XCD x's list of items left to the tile routine at
+// work[WORK_LIST + WORK_STRIDE * x] and the word after it.  Item i belongs to XCD i * NXCD / total.
 constexpr int NXCD = 8;           // XCDs of the MI355X
 constexpr int WORK_CTR = 16, WORK_STRIDE = 16;
 constexpr int WORK_LIST = WORK_CTR + WORK_STRIDE * NXCD;

@@ -1850,7 +1850,11 @@ __global__ __launch_bounds__(256) void thr_bounds_kernel(const QueryDev* __restr
         if (r != PRE_SETTLED) {   // left to the tile routine: onto its XCD's list
             const uint32_t x = (uint32_t)((uint64_t)it * NXCD / total);
             const uint32_t lo = (uint32_t)(((uint64_t)total * x + NXCD - 1) / NXCD);   // first item of XCD x
-            list[lo + atomicAdd(&work[WORK_LIST + WORK_STRIDE * x], 1u)] = it;
+            const uint32_t hi = (uint32_t)(((uint64_t)total * (x + 1u) + NXCD - 1) / NXCD);
+            // wide queries' items from the front, the others from the back, so that the tile
+            // routine takes the long items first and the short ones fill the end of the launch
+            if (q.N >= 128u) list[lo + atomicAdd(&work[WORK_LIST + WORK_STRIDE * x], 1u)] = it;
+            else list[hi - 1u - atomicAdd(&work[WORK_LIST + WORK_STRIDE * x + 1], 1u)] = it;
         }
         if (item_t) {   // ticks of the tile routine (none for a settled tile), then of this wavefront
             if (r == PRE_SETTLED) item_t[it] = 0u;
@@ -1879,27 +1883,34 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_batch_kernel(const QueryDev* __r
         // an XCD's workgroups have at least 64 runs each to share, else of single items (a short
         // batch split into long runs would leave workgroups idle).
         if (threadIdx.x < 64) {
-            uint32_t c = 0, n = 0, base = 0;
+            uint32_t c = 0, n = 0, base = 0, nfront = 0, top = 0;
             if (threadIdx.x == 0) {
                 const uint32_t per = (gridDim.x + NXCD - 1) / NXCD;   // workgroups per XCD
                 for (uint32_t d = 0; d < (uint32_t)NXCD; ++d) {
                     const uint32_t x = (x0 + d) % (uint32_t)NXCD;
                     const uint32_t lo = (uint32_t)(((uint64_t)total * x + NXCD - 1) / NXCD);
-                    const uint32_t len = list ? __hip_atomic_load(&work[WORK_LIST + WORK_STRIDE * x], __ATOMIC_RELAXED,
-                                                                  __HIP_MEMORY_SCOPE_AGENT)
-                                              : (uint32_t)(((uint64_t)total * (x + 1u) + NXCD - 1) / NXCD) - lo;
+                    const uint32_t hi = (uint32_t)(((uint64_t)total * (x + 1u) + NXCD - 1) / NXCD);
+                    uint32_t len = hi - lo, nf = len;
+                    if (list) {   // the list's front part, then its back part in reverse
+                        nf = __hip_atomic_load(&work[WORK_LIST + WORK_STRIDE * x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        len = nf + __hip_atomic_load(&work[WORK_LIST + WORK_STRIDE * x + 1], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                    }
                     if (len == 0) continue;
                     const uint32_t k = max(1u, min(CLAIM_ITEMS, len / (64u * per)));
                     c = atomicAdd(&work[WORK_CTR + WORK_STRIDE * x], k);
-                    if (c < len) { base = lo; n = min(k, len - c); break; }
+                    if (c < len) { base = lo; n = min(k, len - c); nfront = nf; top = hi; break; }
                 }
             }
             c = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
             n = (uint32_t)__builtin_amdgcn_readfirstlane((int)n);
             base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+            nfront = (uint32_t)__builtin_amdgcn_readfirstlane((int)nfront);
+            top = (uint32_t)__builtin_amdgcn_readfirstlane((int)top);
             const uint32_t j = threadIdx.x;
             if (j < n) {
-                const uint32_t it = list ? list[base + c + j] : base + c + j;
+                const uint32_t cj = c + j;
+                const uint32_t it = list ? list[cj < nfront ? base + cj : top - 1u - (cj - nfront)] : base + cj;
                 s_it[j] = it;
                 s_q[j] = nq > 1u ? tq[it] : 0u;   // query of the item (a batch of one needs none)
                 s_pre[j] = pre ? pre[it] : PRE_NONE;
@@ -1953,6 +1964,7 @@ __global__ void bump_epoch_kernel(uint32_t* work) {
     for (int x = 0; x < NXCD; ++x) {
         work[WORK_CTR + WORK_STRIDE * x] = 0u;
         work[WORK_LIST + WORK_STRIDE * x] = 0u;
+        work[WORK_LIST + WORK_STRIDE * x + 1] = 0u;
     }
 }
 
