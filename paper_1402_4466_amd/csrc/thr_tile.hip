@@ -1829,18 +1829,33 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_max_kernel(QueryDev q, con
 // turn.  qtile[i] = first item of query i (qtile[nq] = total); tq[i] = query of item i.
 // item_t (null: off): per item, the wall-clock ticks its workgroup spent on it, the
 // measure of each query's cost inside a batch.
-// Bounds pre-pass of a batch: one wavefront per item.
+// Bounds pre-pass of a batch: one wavefront per item.  PRE_TB: tiles per block of the item order
+// (16 measured best between 1 and 128).
+constexpr uint32_t PRE_TB = 16u;
 __global__ __launch_bounds__(256) void thr_bounds_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
                                                           const uint32_t* __restrict__ tq, uint32_t nq, uint32_t total,
                                                           const uint32_t* epoch_ptr, uint32_t* __restrict__ pre,
                                                           uint32_t* __restrict__ pmask, uint32_t* __restrict__ list,
-                                                          uint32_t* work, uint32_t* __restrict__ item_t) {
-    // workgroup b runs on XCD b % NXCD: each XCD takes a contiguous share of the items, so the
-    // tiles of a query that share its descriptors and quarter-count lines meet in one L2
+                                                          uint32_t* work, uint32_t* __restrict__ item_t, uint32_t tiles) {
+    // workgroup b runs on XCD b % NXCD: each XCD takes a contiguous share [a, e) of the items
     const uint32_t nwg = gridDim.x, x = blockIdx.x % (uint32_t)NXCD;
-    const uint32_t wg = x * (nwg / NXCD) + min(x, nwg % NXCD) + blockIdx.x / (uint32_t)NXCD;
-    const uint32_t it = wg * 4u + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t per = nwg / NXCD, ext = nwg % NXCD;
+    const uint32_t wg0 = x * per + min(x, ext);
+    uint32_t it = (wg0 + blockIdx.x / (uint32_t)NXCD) * 4u + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (it >= total) return;
+    // a share of whole queries (every query of a batch has the same tiles) is taken in blocks of
+    // PRE_TB tiles: block 0 of every query of the share, then block 1, and so on.  The XCDs then
+    // read the same tiles of the pool's records at about the same time, and a record that many
+    // queries name is more likely still cached when the next of them reads it; inside a block
+    // the tiles of a query stay together (they share its descriptors and count lines)
+    const uint32_t a = wg0 * 4u, e = min((wg0 + per + (x < ext ? 1u : 0u)) * 4u, total);
+    if (tiles > 1u && a % tiles == 0u && e % tiles == 0u) {
+        const uint32_t nqx = (e - a) / tiles, l = it - a;
+        const uint32_t TB = min(PRE_TB, tiles);
+        const uint32_t B = l / (nqx * TB), r = l - B * nqx * TB;
+        const uint32_t tb = min(TB, tiles - B * TB);
+        it = a + (r / tb) * tiles + B * TB + r % tb;
+    }
     const uint64_t t0 = item_t ? wall_clock64() : 0ull;
     const uint32_t qi = nq > 1u ? tq[it] : 0u;
     const QueryDev q = qs[qi];
@@ -2034,7 +2049,7 @@ hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_
     if ((pre == nullptr) != (list == nullptr) || (pre && !pmask)) return hipErrorInvalidValue;
     if (pre)
         hipLaunchKernelGGL(thr_bounds_kernel, dim3((total + 3) / 4), dim3(256), 0, s, qs, qtile, tq, nq, total, epoch_ptr,
-                           pre, pmask, list, work, item_t);
+                           pre, pmask, list, work, item_t, nq ? total / nq : 0u);   // tiles per query
     switch (win_batch) {
         case 4: hipLaunchKernelGGL(thr_batch_kernel<4>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
                                    epoch_ptr, err, item_t, pre, pmask, list); break;
