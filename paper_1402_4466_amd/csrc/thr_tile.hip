@@ -1832,7 +1832,8 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_max_kernel(QueryDev q, con
 // Bounds pre-pass of a batch: one wavefront per item.  PRE_TB: tiles per block of the item order
 // (16 measured best between 1 and 128).
 constexpr uint32_t PRE_TB = 16u;
-__global__ __launch_bounds__(256) void thr_bounds_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
+constexpr uint32_t PRE_WG = 4u;   // wavefronts per workgroup (2 as fast; 8 and 16 slower)
+__global__ __launch_bounds__(64 * PRE_WG) void thr_bounds_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
                                                           const uint32_t* __restrict__ tq, uint32_t nq, uint32_t total,
                                                           const uint32_t* epoch_ptr, uint32_t* __restrict__ pre,
                                                           uint32_t* __restrict__ pmask, uint32_t* __restrict__ list,
@@ -1841,14 +1842,14 @@ __global__ __launch_bounds__(256) void thr_bounds_kernel(const QueryDev* __restr
     const uint32_t nwg = gridDim.x, x = blockIdx.x % (uint32_t)NXCD;
     const uint32_t per = nwg / NXCD, ext = nwg % NXCD;
     const uint32_t wg0 = x * per + min(x, ext);
-    uint32_t it = (wg0 + blockIdx.x / (uint32_t)NXCD) * 4u + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    uint32_t it = (wg0 + blockIdx.x / (uint32_t)NXCD) * PRE_WG + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (it >= total) return;
     // a share of whole queries (every query of a batch has the same tiles) is taken in blocks of
     // PRE_TB tiles: block 0 of every query of the share, then block 1, and so on.  The XCDs then
     // read the same tiles of the pool's records at about the same time, and a record that many
     // queries name is more likely still cached when the next of them reads it; inside a block
     // the tiles of a query stay together (they share its descriptors and count lines)
-    const uint32_t a = wg0 * 4u, e = min((wg0 + per + (x < ext ? 1u : 0u)) * 4u, total);
+    const uint32_t a = wg0 * PRE_WG, e = min((wg0 + per + (x < ext ? 1u : 0u)) * PRE_WG, total);
     if (tiles > 1u && a % tiles == 0u && e % tiles == 0u) {
         const uint32_t nqx = (e - a) / tiles, l = it - a;
         const uint32_t TB = min(PRE_TB, tiles);
@@ -2013,8 +2014,8 @@ hipError_t set_smem_limits(size_t max_bytes) {
 
 int pre_waves_per_cu() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)thr_bounds_kernel, 256, 0) != hipSuccess) return 4;
-    return n > 0 ? 4 * n : 4;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)thr_bounds_kernel, 64 * PRE_WG, 0) != hipSuccess) return (int)PRE_WG;
+    return n > 0 ? (int)PRE_WG * n : (int)PRE_WG;
 }
 
 int batch_blocks_per_cu(size_t smem) {
@@ -2048,7 +2049,7 @@ hipError_t launch_batch(const QueryDev* qs, const uint32_t* qtile, const uint32_
                         uint32_t* list) {
     if ((pre == nullptr) != (list == nullptr) || (pre && !pmask)) return hipErrorInvalidValue;
     if (pre)
-        hipLaunchKernelGGL(thr_bounds_kernel, dim3((total + 3) / 4), dim3(256), 0, s, qs, qtile, tq, nq, total, epoch_ptr,
+        hipLaunchKernelGGL(thr_bounds_kernel, dim3((total + PRE_WG - 1) / PRE_WG), dim3(64 * PRE_WG), 0, s, qs, qtile, tq, nq, total, epoch_ptr,
                            pre, pmask, list, work, item_t, nq ? total / nq : 0u);   // tiles per query
     switch (win_batch) {
         case 4: hipLaunchKernelGGL(thr_batch_kernel<4>, dim3(grid), dim3(BLOCK), smem, s, qs, qtile, tq, nq, table, work,
