@@ -8,7 +8,9 @@ MI355X).
   items before it allocates anything (a 32-bit sum would wrap and size the tile states
   too small);
 * inputs built so that the quarter-word bounds leave every word in play and the 8-row
-  bounds settle whole tiles, with a hot spot where neither may prune.
+  bounds settle whole tiles, with a hot spot where neither may prune;
+* a batch whose items split into whole queries per XCD share, so that the bounds pre-pass
+  takes them in blocks of tiles across queries, with a ragged last block.
 """
 import sys
 
@@ -184,6 +186,47 @@ def test_query_busy_times_with_and_without_prepass(G):
             _say(f"busy times, pre-pass {pre}: max {t.max():.1f} us")
             assert np.all(np.isfinite(t)) and np.all(t > 0) and np.all(t < 1e5), (pre, t)
         assert E.device_errors() == 0
+    finally:
+        batch.free()
+        for b in bms:
+            b.release()
+
+
+def test_prepass_block_order_with_ragged_last_block(G):
+    """32 queries of 37 tiles: 1,184 items in 296 workgroups of the pre-pass, 148 items (4 whole
+    queries) per XCD share, taken in blocks of 16, 16 and 5 tiles across the share's queries.
+    Every output equals the oracle's with the pre-pass on and off."""
+    import torch
+    E = G.lib()
+    n_bits = 36 * 512 * 64 + 5000          # 37 tiles, the last one ragged
+    pool_n = 40
+    d = D.pool_densities(pool_n, seed=6161)
+    pool = D.bitmaps(D.IID, d, 0.0, n_bits, [D.key(6161, k) for k in range(pool_n)])
+    bms = E.register_many(pool, n_bits)
+    rng = np.random.default_rng(6161)
+    qs = []
+    for i in range(32):
+        n = int(rng.integers(2, 16))
+        idx = rng.choice(pool_n, size=n, replace=False).astype(np.uint32)
+        qs.append((idx, int(rng.integers(1, n + 1))))
+    outs, ns, caps = [], [], []
+    for idx, _ in qs:
+        o, n, c = G.alloc_out(n_bits, int(sum(len(pool[i]) for i in idx)))
+        outs.append(o); ns.append(n); caps.append(c)
+    wants = [O.threshold([pool[i] for i in idx], n_bits, T, want_hist=False)[0] for idx, T in qs]
+    batch = E.Batch(bms, qs, [o.data_ptr() for o in outs], caps, [n.data_ptr() for n in ns], use_graph=True)
+    try:
+        for pre in (True, False, True):
+            batch.set_prepass(pre)
+            _say(f"pre-pass block order: 32 queries x 37 tiles, pre-pass {pre}")
+            for o in outs:
+                o.fill_(-1)
+            batch.run()
+            torch.cuda.synchronize()
+            assert E.device_errors() == 0
+            for i, (idx, T) in enumerate(qs):
+                got = G.fetch(outs[i], ns[i])
+                assert np.array_equal(got, wants[i]), (pre, i, len(idx), T)
     finally:
         batch.free()
         for b in bms:
