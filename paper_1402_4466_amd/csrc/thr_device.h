@@ -288,7 +288,8 @@ struct InlineIds {
 };
 
 // Host-side launchers (defined with the kernels).  ids: the slots when q.ids is null
-// (threshold queries of at most IDS_INLINE inputs only).
+// (threshold queries of at most IDS_INLINE inputs only).  launch_batch: every query of a batch
+// has the same number of tiles (total / nq; the pre-pass orders its items by it).
 hipError_t launch_query(const QueryDev& q, const BitmapDev* table, uint32_t* ticket, uint32_t epoch, uint32_t* err,
                         hipStream_t s, uint32_t pred_kind = PRED_THRESHOLD,   // kind of *q.pd
                         const InlineIds* ids = nullptr);
