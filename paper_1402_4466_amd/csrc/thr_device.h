@@ -269,6 +269,20 @@ enum : uint32_t {
 constexpr int PRE_MASK_WORDS = TW / 32;
 constexpr uint32_t CLAIM_ITEMS = 4;   // items a workgroup of the batched launch claims at once
 
+// Order in which the bounds pre-pass takes the items of one XCD's share [a, e) of a batch whose
+// queries all have `tiles` tiles: a share of whole queries goes in blocks of PRE_TB tiles, block 0
+// of every query of the share, then block 1, and so on (the last block may be shorter); any other
+// share in item order.  Maps the share onto itself one to one; it is in [a, e).
+constexpr uint32_t PRE_TB = 16u;   // measured best between 1 and 128
+__host__ __device__ inline uint32_t pre_item_order(uint32_t it, uint32_t a, uint32_t e, uint32_t tiles) {
+    if (tiles <= 1u || a % tiles != 0u || e % tiles != 0u) return it;
+    const uint32_t nqx = (e - a) / tiles, l = it - a;   // queries of the share, rank in it
+    const uint32_t TB = tiles < PRE_TB ? tiles : PRE_TB;
+    const uint32_t B = l / (nqx * TB), r = l - B * nqx * TB;   // block, rank inside it
+    const uint32_t tb = tiles - B * TB < TB ? tiles - B * TB : TB;
+    return a + (r / tb) * tiles + B * TB + r % tb;
+}
+
 // LDS bytes needed by the tile routine for a query with N inputs.
 __host__ __device__ inline size_t tile_smem_bytes(uint32_t N) {
     size_t P = (size_t)planes_for(N);

@@ -1829,9 +1829,7 @@ __global__ __launch_bounds__(BLOCK, 4) void thr_query_max_kernel(QueryDev q, con
 // turn.  qtile[i] = first item of query i (qtile[nq] = total); tq[i] = query of item i.
 // item_t (null: off): per item, the wall-clock ticks its workgroup spent on it, the
 // measure of each query's cost inside a batch.
-// Bounds pre-pass of a batch: one wavefront per item.  PRE_TB: tiles per block of the item order
-// (16 measured best between 1 and 128).
-constexpr uint32_t PRE_TB = 16u;
+// Bounds pre-pass of a batch: one wavefront per item.
 constexpr uint32_t PRE_WG = 4u;   // wavefronts per workgroup (2 as fast; 8 and 16 slower)
 __global__ __launch_bounds__(64 * PRE_WG) void thr_bounds_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ qtile,
                                                           const uint32_t* __restrict__ tq, uint32_t nq, uint32_t total,
@@ -1850,13 +1848,7 @@ __global__ __launch_bounds__(64 * PRE_WG) void thr_bounds_kernel(const QueryDev*
     // queries name is more likely still cached when the next of them reads it; inside a block
     // the tiles of a query stay together (they share its descriptors and count lines)
     const uint32_t a = wg0 * PRE_WG, e = min((wg0 + per + (x < ext ? 1u : 0u)) * PRE_WG, total);
-    if (tiles > 1u && a % tiles == 0u && e % tiles == 0u) {
-        const uint32_t nqx = (e - a) / tiles, l = it - a;
-        const uint32_t TB = min(PRE_TB, tiles);
-        const uint32_t B = l / (nqx * TB), r = l - B * nqx * TB;
-        const uint32_t tb = min(TB, tiles - B * TB);
-        it = a + (r / tb) * tiles + B * TB + r % tb;
-    }
+    it = pre_item_order(it, a, e, tiles);
     const uint64_t t0 = item_t ? wall_clock64() : 0ull;
     const uint32_t qi = nq > 1u ? tq[it] : 0u;
     const QueryDev q = qs[qi];

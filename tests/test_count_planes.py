@@ -7,7 +7,8 @@ and general symmetric tables.  These helpers are __host__ __device__ functions o
 kernel header; tests/csrc/count_planes_check.cpp includes that header, builds for the
 host only and checks them against integer arithmetic for every count 0..N' and every
 threshold, N' <= 1024.  The layout helpers of the fine presence records are checked the same
-way (tests/csrc/record_layout_check.cpp).
+way (tests/csrc/record_layout_check.cpp), and so is the bounds pre-pass's item order
+(tests/csrc/pre_order_check.cpp).
 """
 import os
 import subprocess
@@ -34,6 +35,20 @@ def test_presence_record_layout(tmp_path):
     subprocess.run([HIPCC, "-x", "hip", "--offload-host-only", "-O2", "-std=c++17",
                     "-I", os.path.join(ROOT, "paper_1402_4466_amd", "csrc"), "-o", exe,
                     os.path.join(ROOT, "tests", "csrc", "record_layout_check.cpp")],
+                   check=True, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    r = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.startswith("ok"), r.stdout
+
+
+def test_prepass_item_order(tmp_path):
+    """The bounds pre-pass's item order maps every XCD share of a batch onto itself one to one and
+    takes a share of whole queries in blocks of tiles across its queries, for every batch of up to
+    72 queries of up to 70 tiles, larger batches and workgroups of 1 to 16 wavefronts
+    (tests/csrc/pre_order_check.cpp)."""
+    exe = str(tmp_path / "pre_order_check")
+    subprocess.run([HIPCC, "-x", "hip", "--offload-host-only", "-O2", "-std=c++17",
+                    "-I", os.path.join(ROOT, "paper_1402_4466_amd", "csrc"), "-o", exe,
+                    os.path.join(ROOT, "tests", "csrc", "pre_order_check.cpp")],
                    check=True, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
     r = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=300)
     assert r.returncode == 0 and r.stdout.startswith("ok"), r.stdout
